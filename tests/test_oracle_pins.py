@@ -1,0 +1,490 @@
+"""Pins of the FP64 oracle against closed forms, invariants, published constants and
+brute force, so that a plausible slip in the oracle (a dropped term, a wrong sign or
+index, a transposed operand) fails here. CPU only."""
+
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden_rows(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as fh:
+        for line in fh:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append(line)
+    return rows
+
+
+# ------------------------------------------------------------------ colour (footnote of Section 3)
+
+def test_ycc_matches_published_bt601_matrix():
+    rows = _golden_rows("bt601_full_range.txt")
+    M = np.array([[float(v) for v in r.split()] for r in rows[:3]])
+    off = np.array([float(v) for v in rows[3].split()[1:]])
+    rgb = np.random.default_rng(0).uniform(0, 1, (3, 5, 7))
+    want = np.einsum("ij,jhw->ihw", M, rgb) + off[:, None, None]
+    assert np.max(np.abs(O.rgb_to_ycc(rgb) - want)) < 2e-6
+
+
+def test_ycc_grey_and_round_trip():
+    v = np.linspace(0, 1, 11)
+    grey = np.stack([v, v, v])[:, None, :]
+    ycc = O.rgb_to_ycc(grey)
+    assert np.max(np.abs(ycc[0] - v)) < 1e-15
+    assert np.max(np.abs(ycc[1:] - 0.5)) < 1e-15
+    rgb = np.random.default_rng(1).uniform(0, 1, (3, 6, 4))
+    assert np.max(np.abs(O.ycc_to_rgb(O.rgb_to_ycc(rgb)) - rgb)) < 1e-14
+
+
+# ------------------------------------------------------------------ pyramid (Section 4)
+
+def test_down2_weights_closed_form():
+    rows = _golden_rows("down2_bicubic_weights.txt")
+    num = np.array([float(v) for v in rows[0].split()])
+    assert np.array_equal(O.down2_weights() * 1024.0, num)
+    assert O.down2_weights().sum() == 1.0
+    gain = float(rows[1])
+    assert abs((O.down2_weights() ** 2).sum() - gain) < 1e-15
+
+
+def test_down2_constant_sizes_and_ramp():
+    for H, W in [(1, 1), (3, 5), (8, 8), (33, 17)]:
+        x = np.full((2, H, W), 0.37)
+        y = O.down2(x)
+        assert y.shape == (2, (H + 1) // 2, (W + 1) // 2)
+        assert np.max(np.abs(y - 0.37)) < 1e-15
+    # a linear ramp is reproduced exactly at the output sample positions 2m + 1/2
+    H, W = 40, 48
+    yy, xx = np.mgrid[0:H, 0:W].astype(float)
+    alpha, beta, c0 = 0.013, -0.007, 0.4
+    x = (c0 + alpha * xx + beta * yy)[None]
+    y = O.down2(x)[0]
+    m_y, m_x = np.mgrid[0:H // 2, 0:W // 2].astype(float)
+    want = c0 + alpha * (2 * m_x + 0.5) + beta * (2 * m_y + 0.5)
+    inner = (slice(2, H // 2 - 2), slice(2, W // 2 - 2))
+    assert np.max(np.abs(y[inner] - want[inner])) < 1e-14
+
+
+def test_down2_halves_noise():
+    """The paper: downsampling by two roughly halves the noise level (Section 4)."""
+    n = np.random.default_rng(5).standard_normal((1, 1024, 1024))
+    g = O.down2(n)[0][8:-8, 8:-8].std()
+    assert abs(g - 0.40442) < 0.004
+
+
+def test_down2_brute_force():
+    x = np.random.default_rng(3).uniform(0, 1, (1, 7, 9))
+    w = [-12, -36, 116, 444, 444, 116, -36, -12]
+    H, W = 7, 9
+    out = np.zeros((4, 5))
+    for m in range(4):
+        for n in range(5):
+            acc = 0.0
+            for i, ty in enumerate(range(-3, 5)):
+                for j, tx in enumerate(range(-3, 5)):
+                    yy = min(max(2 * m + ty, 0), H - 1)
+                    xx = min(max(2 * n + tx, 0), W - 1)
+                    acc += w[i] * w[j] * x[0, yy, xx]
+            out[m, n] = acc / 1024.0 / 1024.0
+    assert np.max(np.abs(O.down2(x)[0] - out)) < 1e-14
+
+
+# ------------------------------------------------------------------ selection (Section 3, Eq. (3)-(6))
+
+def _ramp(H, W, alpha, beta, C=3, c0=0.3):
+    yy, xx = np.mgrid[0:H, 0:W].astype(float)
+    return np.stack([c0 + alpha * xx + beta * yy] * C)
+
+
+@pytest.mark.parametrize("alpha,beta", [(0.01, 0.0), (0.0, 0.02), (0.011, 0.004), (-0.006, 0.013), (0.009, -0.009)])
+def test_ramp_orientation_strength_coherence(alpha, beta):
+    H, W, C = 20, 24, 3
+    z = _ramp(H, W, alpha, beta, C)
+    gx, gy = O.gradients(z)
+    inner = (slice(1, H - 1), slice(1, W - 1))
+    assert np.max(np.abs(gx[:, 1:-1, 1:-1] - alpha)) < 1e-15
+    assert np.max(np.abs(gy[:, 1:-1, 1:-1] - beta)) < 1e-15
+    a, b, c = O.structure_tensor(z)
+    theta, strength, coh = O.eigen_features(a, b, c)
+    core = (slice(3, H - 3), slice(3, W - 3))
+    want_theta = np.mod(np.arctan2(beta, alpha) + np.pi / 2, np.pi)
+    d = np.abs(theta[core] - want_theta)
+    d = np.minimum(d, np.pi - d)
+    assert np.max(d) < 1e-7
+    assert np.max(np.abs(strength[core] - np.sqrt(C * (alpha ** 2 + beta ** 2)))) < 1e-15
+    assert np.min(coh[core]) > 1 - 1e-6
+    del inner
+
+
+def test_orientation_is_edge_direction():
+    """A vertical edge (intensity varies along x) has orientation pi/2 (the edge runs along y)."""
+    z = np.zeros((3, 16, 16))
+    z[:, :, 8:] = 1.0
+    a, b, c = O.structure_tensor(z)
+    theta, strength, coh = O.eigen_features(a, b, c)
+    assert abs(theta[8, 8] - np.pi / 2) < 1e-12 and coh[8, 8] > 0.999
+    zt = np.transpose(z, (0, 2, 1)).copy()   # horizontal edge
+    a, b, c = O.structure_tensor(zt)
+    theta, _, _ = O.eigen_features(a, b, c)
+    assert min(theta[8, 8], np.pi - theta[8, 8]) < 1e-12
+
+
+def test_features_against_eigh_and_mpmath():
+    import mpmath as mp
+    mp.mp.dps = 50
+    rng = np.random.default_rng(7)
+    a = rng.uniform(0, 1, 200) ** 3
+    c = rng.uniform(0, 1, 200) ** 3
+    b = rng.uniform(-1, 1, 200) * np.sqrt(a * c)
+    theta, strength, coh = O.eigen_features(a, b, c)
+    for i in range(200):
+        T = np.array([[a[i], b[i]], [b[i], c[i]]])
+        w, V = np.linalg.eigh(T)       # ascending eigenvalues
+        minor = V[:, 0]
+        ang = np.mod(np.arctan2(minor[1], minor[0]), np.pi)
+        d = abs(ang - theta[i])
+        assert min(d, np.pi - d) < 1e-7
+        am, bm, cm = mp.mpf(a[i]), mp.mpf(b[i]), mp.mpf(c[i])
+        tr = am + cm
+        mu = mp.sqrt((am - cm) ** 2 + 4 * bm * bm)
+        l1, l2 = (tr + mu) / 2, max((tr - mu) / 2, mp.mpf(0))
+        assert abs(float(mp.sqrt(l1)) - strength[i]) < 1e-14
+        cm_ = (mp.sqrt(l1) - mp.sqrt(l2)) / (mp.sqrt(l1) + mp.sqrt(l2))
+        assert abs(float(cm_) - coh[i]) < 1e-7 * max(1.0, float(mp.sqrt(l1 / max(l2, mp.mpf(1e-300)))) * 1e-8)
+
+
+def _structure_tensor_exact(z_frac, H, W, C, r=2):
+    """Eq. (5)-(6) literally, in exact rational arithmetic: sum_j w_j G_j G_j^T with the
+    2 x C colour Jacobian G_j, box weights 1/25, all indices clamped."""
+    def cl(v, n):
+        return min(max(v, 0), n - 1)
+
+    def jac(y, x):
+        G = [[None] * C, [None] * C]
+        for ch in range(C):
+            G[0][ch] = (z_frac[ch][y][cl(x + 1, W)] - z_frac[ch][y][cl(x - 1, W)]) / 2
+            G[1][ch] = (z_frac[ch][cl(y + 1, H)][x] - z_frac[ch][cl(y - 1, H)][x]) / 2
+        return G
+
+    n = (2 * r + 1) ** 2
+    T = {}
+    for y in range(H):
+        for x in range(W):
+            acc = [[Fraction(0)] * 2 for _ in range(2)]
+            for dy in range(-r, r + 1):
+                for dx in range(-r, r + 1):
+                    G = jac(cl(y + dy, H), cl(x + dx, W))
+                    for p in range(2):
+                        for q in range(2):
+                            acc[p][q] += sum(G[p][ch] * G[q][ch] for ch in range(C)) / n
+            T[y, x] = acc
+    return T
+
+
+@pytest.mark.parametrize("H,W,C", [(1, 1, 3), (3, 5, 3), (7, 6, 1), (9, 7, 3)])
+def test_structure_tensor_exact_rational(H, W, C):
+    rng = np.random.default_rng(H * 100 + W)
+    k = rng.integers(0, 256, (C, H, W))
+    z = k / 255.0
+    zf = [[[Fraction(int(k[ch, y, x]), 255) for x in range(W)] for y in range(H)] for ch in range(C)]
+    T = _structure_tensor_exact(zf, H, W, C)
+    a, b, c = O.structure_tensor(z)
+    for (y, x), t in T.items():
+        scale = float(t[0][0] + t[1][1]) + 1e-300
+        assert abs(float(t[0][0]) - a[y, x]) <= 1e-14 * scale
+        assert abs(float(t[0][1]) - b[y, x]) <= 1e-14 * scale
+        assert abs(float(t[1][0]) - b[y, x]) <= 1e-14 * scale
+        assert abs(float(t[1][1]) - c[y, x]) <= 1e-14 * scale
+
+
+def test_constant_image_flat_bucket():
+    for q_theta in (16, 24):
+        z = np.full((3, 12, 10), 0.42)
+        s = O.select(z, q_theta, [0.01, 0.02], [0.3, 0.6])
+        assert np.all(s == ((q_theta // 2) * 3 + 0) * 3 + 0)
+
+
+def test_quantize_layout_and_ties():
+    theta = np.array([0.0, np.pi / 24 * 1.5, np.pi - 1e-12, np.pi / 2])
+    st = np.array([0.1, 0.2, 0.3, 0.2])
+    co = np.array([0.5, 0.6, 0.0, 0.99])
+    s = O.quantize(theta, st, co, 24, [0.2, 0.3], [0.6, 0.9])
+    # bins: theta -> 0, 1, 23, 12; strength: 0, 1 (tie goes up), 2, 1; coherence: 0, 1 (tie), 0, 2
+    want = [(0 * 3 + 0) * 3 + 0, (1 * 3 + 1) * 3 + 1, (23 * 3 + 2) * 3 + 0, (12 * 3 + 1) * 3 + 2]
+    assert list(s) == want
+
+
+def _rot90_fixture(seed):
+    z, _ = synth.noisy_pair(seed, 48, 48, 3, 25)
+    return z.astype(np.float64)
+
+
+def test_rot90_shifts_orientation_by_half_the_bins():
+    z = _rot90_fixture(11)
+    q = 24
+    t_s, t_c = [0.02, 0.05], [0.2, 0.5]
+    s, m = O.select(z, q, t_s, t_c, return_margin=True)
+    zr = np.rot90(z, 1, axes=(1, 2)).copy()
+    sr, mr = O.select(zr, q, t_s, t_c, return_margin=True)
+    s_back = np.rot90(sr, -1)
+    ok = (m > 1e-9) & (np.rot90(mr, -1) > 1e-9)
+    qs_qc = 9
+    assert ok.sum() > 1500
+    assert np.all((s_back % qs_qc)[ok] == (s % qs_qc)[ok])
+    assert np.all(((s_back // qs_qc) % q)[ok] == ((s // qs_qc + q // 2) % q)[ok])
+
+
+def test_flip_mirrors_orientation():
+    z = _rot90_fixture(12)
+    q = 24
+    t_s, t_c = [0.02, 0.05], [0.2, 0.5]
+    s, m = O.select(z, q, t_s, t_c, return_margin=True)
+    sf, mf = O.select(z[:, :, ::-1].copy(), q, t_s, t_c, return_margin=True)
+    sf = sf[:, ::-1]
+    ok = (m > 1e-9) & (mf[:, ::-1] > 1e-9)
+    assert ok.sum() > 1500
+    assert np.all((sf % 9)[ok] == (s % 9)[ok])
+    assert np.all(((sf // 9))[ok] == (q - 1 - s // 9)[ok])
+
+
+def test_margin_detects_boundary():
+    a = np.array([1.0, 1.0, 1.0])
+    c = np.array([0.5, 1.0, 0.2])
+    b = np.array([0.0, 0.0, 0.3])
+    th, st, co = O.eigen_features(a, b, c)
+    m = O.select_margins(a, b, c, th, st, co, 24, [st[2]], [])
+    assert m[0] < 1e-12          # a > c, b = 0: theta = pi/2 exactly on a boundary (bin 12 edge)
+    assert m[1] == 0.0           # isotropic
+    assert m[2] == 0.0           # strength equal to the threshold
+
+
+# ------------------------------------------------------------------ filtering (Eq. (1), (9)-(10))
+
+def _bank_level(K_theta, t_s, t_c, rg, rf, coeffs):
+    return O.LevelBank(K_theta, np.asarray(t_s, float), np.asarray(t_c, float), rg, rf, coeffs)
+
+
+def test_delta_filter_is_identity_single_scale():
+    z, _ = synth.noisy_pair(3, 19, 23, 3, 25)
+    K = 24 * 9
+    co = np.zeros((K, 3, 49))
+    co[:, :, 24] = 1.0
+    lb = _bank_level(24, [0.02, 0.05], [0.2, 0.5], 3, None, co)
+    out = O.denoise(z, O.Bank([lb]))
+    assert np.max(np.abs(out - z)) < 1e-14
+
+
+def test_delta_filters_multiscale():
+    z, _ = synth.noisy_pair(4, 37, 29, 3, 25)
+    K = 24 * 9
+    g_only = np.zeros((K, 3, 98))
+    g_only[:, :, 49 + 24] = 1.0
+    levels = [_bank_level(24, [0.02, 0.05], [0.2, 0.5], 3, 3, g_only) for _ in range(3)]
+    out = O.denoise(z, O.Bank(levels))
+    assert np.max(np.abs(out - z)) < 1e-14
+    # f = delta, g = 0: nearest-neighbour upsampling of the coarser output
+    f_only = np.zeros((K, 3, 98))
+    f_only[:, :, 24] = 1.0
+    lb = _bank_level(24, [0.02, 0.05], [0.2, 0.5], 3, 3, f_only)
+    zf = O.to_filter_space(z)
+    coarse = O.down2(zf)
+    s = O.select(z.astype(float), 24, lb.t_s, lb.t_c)
+    out = O.apply_level(zf, s, lb, u_coarse=coarse)
+    H, W = z.shape[1:]
+    want = coarse[:, np.arange(H)[:, None] // 2, np.arange(W)[None, :] // 2]
+    assert np.max(np.abs(out - want)) < 1e-15
+
+
+def test_apply_brute_force():
+    rng = np.random.default_rng(21)
+    C, H, W = 2, 5, 7
+    z = rng.uniform(0, 1, (C, H, W))
+    uc = rng.uniform(0, 1, (C, 3, 4))
+    K = 4
+    rf, rg = 1, 2
+    co = rng.normal(0, 1, (K, C, 9 + 25))
+    s = rng.integers(0, K, (H, W))
+    lb = _bank_level(1, [], [], rg, rf, co)
+    got = O.apply_level(z, s, lb, u_coarse=uc)
+
+    def cl(v, n):
+        return min(max(v, 0), n - 1)
+    for ch in range(C):
+        for y in range(H):
+            for x in range(W):
+                acc = 0.0
+                t = 0
+                for dy in range(-rf, rf + 1):
+                    for dx in range(-rf, rf + 1):
+                        acc += co[s[y, x], ch, t] * uc[ch, cl(y // 2 + dy, 3), cl(x // 2 + dx, 4)]
+                        t += 1
+                for dy in range(-rg, rg + 1):
+                    for dx in range(-rg, rg + 1):
+                        acc += co[s[y, x], ch, t] * z[ch, cl(y + dy, H), cl(x + dx, W)]
+                        t += 1
+                assert abs(acc - got[ch, y, x]) < 1e-13
+
+
+def test_apply_is_linear_for_fixed_selection():
+    rng = np.random.default_rng(22)
+    z1, z2 = rng.uniform(0, 1, (2, 3, 9, 11))
+    u1, u2 = rng.uniform(0, 1, (2, 3, 5, 6))
+    co = rng.normal(0, 1, (216, 3, 98))
+    s = rng.integers(0, 216, (9, 11))
+    lb = _bank_level(24, [0.1, 0.2], [0.3, 0.6], 3, 3, co)
+    al, be = 0.7, -1.3
+    lhs = O.apply_level(al * z1 + be * z2, s, lb, al * u1 + be * u2)
+    rhs = al * O.apply_level(z1, s, lb, u1) + be * O.apply_level(z2, s, lb, u2)
+    assert np.max(np.abs(lhs - rhs)) < 1e-12
+
+
+def test_constant_fixed_point_dc_normalised():
+    co = synth.random_bank_coeffs(5, 216, 3, 49, 49)      # each filter's taps sum to 1
+    levels = [_bank_level(24, [0.02, 0.05], [0.2, 0.5], 3, 3, co) for _ in range(3)]
+    z = np.full((3, 30, 26), 0.61)
+    out = O.denoise(z, O.Bank(levels))
+    assert np.max(np.abs(out - 0.61)) < 1e-13
+
+
+# ------------------------------------------------------------------ training (Eq. (7)-(8))
+
+def test_ridge_one_dimensional_closed_form():
+    rng = np.random.default_rng(31)
+    x = rng.normal(0, 1, 200)
+    y = 0.7 * x + rng.normal(0, 0.1, 200)
+    st = O.GramStats.zeros(1, 1, 1)
+    st.G[0, 0, 0, 0] = x @ x
+    st.b[0, 0, 0] = x @ y
+    st.n[0] = 200
+    for lam in (0.0, 1e-3, 0.5):
+        h, _ = O.solve_level(st, lam, n_min=1)
+        assert abs(h[0, 0, 0] - (x @ y) / (x @ x + 200 * lam)) < 1e-14
+
+
+def test_planted_single_scale_recovery_matches_lstsq():
+    rng = np.random.default_rng(41)
+    q_theta, r = 4, 2
+    K = q_theta * 2 * 2
+    D = 25
+    planted = rng.normal(0, 0.3, (K, 1, D))
+    zs = [rng.uniform(0, 1, (1, 48, 48)) for _ in range(6)]
+    st, co = (np.concatenate(v) for v in zip(*[O.level_features(z) for z in zs]))
+    t_s, t_c = [float(np.median(st))], [float(np.median(co))]
+    pairs = []
+    for z in zs:
+        s = O.select(z, q_theta, t_s, t_c)
+        u = O.apply_level(z, s, _bank_level(q_theta, t_s, t_c, r, None, planted))
+        pairs.append((z, u))
+    bank, stats, fb = O.train_single(pairs, q_theta, 2, 2, r, 0.0, t_s=t_s, t_c=t_c, n_min=D)
+    assert not fb.any()
+    assert np.max(np.abs(bank.levels[0].coeffs - planted)) < 1e-10
+    # the same per-bucket fit by a library least-squares solve on the stacked samples
+    k = int(np.argmax(stats.n))
+    Xs, ys = [], []
+    for z, u in pairs:
+        s = O.select(z, q_theta, t_s, t_c).ravel()
+        X = O.patch_matrix(z[0], r)
+        Xs.append(X[s == k])
+        ys.append(u[0].ravel()[s == k])
+    X = np.concatenate(Xs)
+    y = np.concatenate(ys)
+    h_ls = np.linalg.lstsq(X, y, rcond=None)[0]
+    assert np.max(np.abs(h_ls - bank.levels[0].coeffs[k, 0])) < 1e-10
+    # residual identity sum (y - x.h)^2 = yy - 2 b.h + h.G.h
+    h = bank.levels[0].coeffs[k, 0]
+    res = np.sum((y - X @ h) ** 2)
+    ident = stats.yy[k, 0] - 2 * stats.b[k, 0] @ h + h @ stats.G[k, 0] @ h
+    assert abs(res - ident) < 1e-9
+
+
+def test_pooled_fallback_is_sum_of_bucket_statistics():
+    rng = np.random.default_rng(43)
+    K, C, D = 5, 1, 3
+    st = O.GramStats.zeros(K, C, D)
+    for k in range(K):
+        X = rng.normal(0, 1, (10 + 5 * k, D))
+        y = rng.normal(0, 1, 10 + 5 * k)
+        st.G[k, 0] = X.T @ X
+        st.b[k, 0] = X.T @ y
+        st.n[k] = len(y)
+    st.n[0] = 2
+    h, fb = O.solve_level(st, 1e-3, n_min=D)
+    assert fb.tolist() == [True, False, False, False, False]
+    Gp, bp, n = st.G[:, 0].sum(0), st.b[:, 0].sum(0), st.n.sum()
+    assert np.max(np.abs(h[0, 0] - np.linalg.solve(Gp / n + 1e-3 * np.eye(D), bp / n))) < 1e-14
+
+
+def test_planted_multiscale_recovery():
+    """Targets generated by a planted two-level cascade are recovered level by level at lambda = 0."""
+    rng = np.random.default_rng(47)
+    q_theta = 2
+    rf, rg = 1, 1
+    K = q_theta * 2
+    D = 18
+    planted = [rng.normal(0, 0.3, (K, 3, D)) for _ in range(2)]
+    pyrs = [O.build_pyramid(rng.uniform(0, 1, (3, 40, 44)), 3) for _ in range(5)]
+    thr = []
+    for lev in range(2):
+        st = np.concatenate([O.level_features(p[lev])[0] for p in pyrs])
+        thr.append(([float(np.median(st))], []))
+    banks = [_bank_level(q_theta, thr[lev][0], thr[lev][1], rg, rf, planted[lev]) for lev in range(2)]
+    # targets: the planted cascade (u^2 = z^2, then level 1, then level 0)
+    targets = []
+    for pz in pyrs:
+        u2 = O.to_filter_space(pz[2])
+        s1 = O.select(pz[1], q_theta, *thr[1])
+        u1 = O.apply_level(O.to_filter_space(pz[1]), s1, banks[1], u2)
+        s0 = O.select(pz[0], q_theta, *thr[0])
+        u0 = O.apply_level(O.to_filter_space(pz[0]), s0, banks[0], u1)
+        targets.append((u0, u1))
+    # level 1 fit from (z^1, u^2 = z^2) against u1; then level 0 from (z^0, fitted level-1 output)
+    st1 = O.GramStats.zeros(K, 3, D)
+    for pz, (_, u1) in zip(pyrs, targets):
+        s1 = O.select(pz[1], q_theta, *thr[1])
+        O.accumulate_level(st1, s1, O.to_filter_space(pz[1]), u1, rg, rf, O.to_filter_space(pz[2]))
+    h1, fb1 = O.solve_level(st1, 0.0)
+    assert not fb1.any()
+    assert np.max(np.abs(h1 - planted[1])) < 1e-9
+    fitted1 = _bank_level(q_theta, thr[1][0], thr[1][1], rg, rf, h1)
+    st0 = O.GramStats.zeros(K, 3, D)
+    for pz, (u0, _) in zip(pyrs, targets):
+        s1 = O.select(pz[1], q_theta, *thr[1])
+        uh1 = O.apply_level(O.to_filter_space(pz[1]), s1, fitted1, O.to_filter_space(pz[2]))
+        s0 = O.select(pz[0], q_theta, *thr[0])
+        O.accumulate_level(st0, s0, O.to_filter_space(pz[0]), u0, rg, rf, uh1)
+    h0, fb0 = O.solve_level(st0, 0.0)
+    assert not fb0.any()
+    assert np.max(np.abs(h0 - planted[0])) < 1e-9
+
+
+def test_train_multiscale_runs_and_denoises():
+    pairs = [synth.noisy_pair(100 + i, 64, 64, 3, 25) for i in range(4)]
+    pairs = [(z.astype(np.float64), u.astype(np.float64)) for z, u in pairs]
+    bank, _, _ = O.train_multiscale(pairs, 2, 8, 2, 2, 2, 2, 1e-3)
+    z, u = synth.noisy_pair(500, 64, 64, 3, 25)
+    out = O.denoise(z, bank)
+    assert O.psnr(out, u) > O.psnr(z, u) + 2.0
+
+
+def test_noise_model_statistics():
+    u = np.full((1, 256, 256), 0.5, dtype=np.float32)
+    z = synth.add_noise(u, 25.0, 9)
+    k = np.rint(z.astype(np.float64) * 255)
+    assert np.max(np.abs(k / 255 - z)) < 1e-7
+    assert abs((z.astype(np.float64) - 0.5).std() * 255 - 25.0) < 0.5
+
+
+def test_thresholds_equal_population():
+    v = np.random.default_rng(3).uniform(0, 1, 30000)
+    t = O.thresholds_from_features(v, 3)
+    counts = [(v < t[0]).sum(), ((v >= t[0]) & (v < t[1])).sum(), (v >= t[1]).sum()]
+    assert max(counts) - min(counts) <= 2
