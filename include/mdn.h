@@ -1,0 +1,143 @@
+/*
+ * mdn.h -- C ABI of the MI355X (gfx950) multiscale adaptive-filter denoiser.
+ *
+ * Method: "Fast, Trainable, Multiscale Denoising" (Choi, Isidoro, Getreuer, Milanfar,
+ * arXiv 1802.06130). A per-pixel filter index s(i) is chosen from features of the
+ * colour structure tensor (Section 3, Eq. (3)-(6)); the selected FIR filter is applied
+ * (Eq. (1)); over a factor-two bicubic pyramid each level upscales the coarser output
+ * and denoises and blends the current level (Section 4, Eq. (9)-(10)); the filters are
+ * fitted per bucket by least squares (Eq. (7)-(8)).
+ *
+ * Conventions shared by every entry point
+ *  - Pixel, index and accumulator pointers are DEVICE pointers owned by the caller.
+ *    The library never frees or retains them past the call's stream work.
+ *  - Threshold arrays in mdn_level are HOST pointers, read during the call.
+ *  - Every call validates its arguments synchronously, then enqueues its work on
+ *    `stream` (a hipStream_t passed as void*; NULL = the null stream) and returns
+ *    without waiting. A non-OK status means nothing was enqueued; the reason is in
+ *    mdn_last_error() (thread-local). Launch failures return MDN_EDEVICE.
+ *  - Images are planar: element (c, y, x) is at data + c*plane_pitch + y*row_pitch + x
+ *    (pitches in elements). Width or height 0 is an empty image: calls on it do nothing
+ *    and return MDN_OK.
+ *  - Borders: every stencil reads clamp-to-edge (replicated) pixels.
+ */
+#ifndef MDN_H
+#define MDN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MDN_OK = 0,
+    MDN_EINVAL = 1,   /* bad argument: null pointer, size mismatch, unknown enum */
+    MDN_ENOMEM = 2,   /* workspace too small */
+    MDN_EDEVICE = 3,  /* HIP launch or runtime error */
+    MDN_ENOTSUP = 4   /* valid but unsupported configuration (filter radius, K > 255, ...) */
+} mdn_status;
+
+typedef enum { MDN_F32 = 0, MDN_F16 = 1 } mdn_dtype;
+
+/* Colour space of an image's channels. Colour images are filtered in full-range
+ * ITU-R BT.601 YCbCr (footnote of Section 3): Y = .299R + .587G + .114B,
+ * Cb = (B - Y)/1.772 + 1/2, Cr = (R - Y)/1.402 + 1/2. The structure tensor is
+ * always taken on RGB. */
+typedef enum { MDN_GRAY = 0, MDN_RGB = 1, MDN_YCC = 2 } mdn_color;
+
+typedef struct {
+    void*   data;         /* device pointer */
+    int32_t width;
+    int32_t height;
+    int32_t channels;     /* 1 (MDN_GRAY) or 3 (MDN_RGB / MDN_YCC) */
+    int32_t dtype;        /* mdn_dtype of the stored elements */
+    int32_t color;        /* mdn_color */
+    int32_t reserved;     /* must be 0 */
+    int64_t row_pitch;    /* elements between rows, >= width */
+    int64_t plane_pitch;  /* elements between channel planes, >= height*row_pitch */
+} mdn_image;
+
+/* Filters and selector of one trained level (Eq. (9)-(10); Eq. (1) when radius_f < 0).
+ * K = q_theta*q_s*q_c buckets, bucket index s = (q_theta_bin*q_s + q_s_bin)*q_c + q_c_bin:
+ *   q_theta_bin: angle of the structure tensor's minor eigenvector (edge direction,
+ *                from +x towards +y, rows downward) in q_theta uniform bins over [0, pi);
+ *   q_s_bin:     number of t_s thresholds that sqrt(lambda1) reaches (>=);
+ *   q_c_bin:     number of t_c thresholds that (sqrt(l1)-sqrt(l2))/(sqrt(l1)+sqrt(l2)) reaches.
+ * The structure tensor sums, over the RGB (or grey) channels, products of central-difference
+ * gradients averaged over a 5x5 box (Eq. (6)); it is evaluated in float64.
+ * coeffs[k][c] holds taps_f = (2*radius_f+1)^2 upscale taps applied to the coarser output at
+ * floor(i/2) + j, then taps_g = (2*radius_g+1)^2 taps applied to this level's input at i + j,
+ * both row-major over (dy, dx). */
+typedef struct {
+    int32_t q_theta;      /* 2..64, even */
+    int32_t q_s;          /* 1..16 */
+    int32_t q_c;          /* 1..16 */
+    int32_t radius_f;     /* -1 (single-scale filter), 1, 2 or 3 */
+    int32_t radius_g;     /* 1, 2 or 3 */
+    int32_t channels;     /* 1 or 3, must match the images */
+    int32_t coeff_dtype;  /* mdn_dtype of coeffs */
+    int32_t reserved;     /* must be 0 */
+    const double* t_s;    /* HOST, q_s-1 ascending strength thresholds */
+    const double* t_c;    /* HOST, q_c-1 ascending coherence thresholds */
+    const void*   coeffs; /* DEVICE, [K][channels][taps_f + taps_g] */
+} mdn_level;
+
+/* A multiscale bank: level[l] filters trained level l, l = 0 (finest) .. levels-1.
+ * The pyramid then has levels+1 levels and the coarsest one passes through unfiltered
+ * (Section 4). A single-scale bank has levels = 1 and radius_f < 0. */
+typedef struct {
+    int32_t levels;
+    int32_t reserved;
+    const mdn_level* level;   /* HOST array of `levels` entries */
+} mdn_bank;
+
+/* Factor-two bicubic pyramid (Section 4, "Multiscale filtering").
+ * out[i] receives level i+1: out[i] = down2(level i), where level 0 is *level0.
+ * down2: Keys cubic (a = -1/2) stretched by two and centred at 2m+1/2, i.e. the separable
+ * 8-tap kernel [-12,-36,116,444,444,116,-36,-12]/1024 over input samples 2m-3..2m+4, rows
+ * then columns; evaluated in float64 and rounded once to the output dtype. Each out[i] must
+ * have width ceil(w_i/2), height ceil(h_i/2), the same channels and colour. */
+mdn_status mdn_pyramid_build(const mdn_image* level0, int32_t n_out, const mdn_image* out,
+                             void* stream);
+
+/* Filter selector s(i) (Section 3, "Filter selection"; Eq. (6); features as in mdn_level).
+ * z: RGB or grey image of the level. s_out: device uint8 [height][s_pitch]. */
+mdn_status mdn_select_filters(const mdn_image* z, const mdn_level* lvl, uint8_t* s_out,
+                              int64_t s_pitch, void* stream);
+
+/* One filtering step (Eq. (1) or Eq. (9)).
+ * z:        this level's noisy input, RGB or grey (colour images are converted to YCbCr for
+ *           filtering, the selector reads RGB).
+ * u_coarse: the coarser level's output (YCbCr, or RGB for the coarsest pyramid level, which
+ *           is converted), size ceil(w/2) x ceil(h/2); NULL iff lvl->radius_f < 0.
+ * s:        precomputed selector (device uint8 [height][s_pitch]) or NULL to select inline.
+ * u_out:    output, YCbCr (intermediate levels) or RGB (converted back), or grey. */
+mdn_status mdn_apply_level(const mdn_image* z, const mdn_image* u_coarse, const uint8_t* s,
+                           int64_t s_pitch, const mdn_level* lvl, const mdn_image* u_out,
+                           void* stream);
+
+/* Bytes of device workspace mdn_denoise needs for a width x height image with `channels`
+ * channels, a bank of `levels` trained levels and pyramid storage dtype `storage`. */
+mdn_status mdn_denoise_workspace_size(int32_t width, int32_t height, int32_t channels,
+                                      int32_t levels, int32_t storage, size_t* bytes);
+
+/* Whole cascade (Section 4): pyramid of `in`, u^L = z^L, then Eq. (9) for l = L-1..0, the
+ * last level written to `out` (RGB or grey, same size as `in`). `storage` is the dtype of the
+ * intermediate pyramid and outputs kept in `ws` (caller-owned device memory of at least
+ * mdn_denoise_workspace_size bytes, 256-byte aligned). A single-scale bank applies Eq. (1). */
+mdn_status mdn_denoise(const mdn_image* in, const mdn_bank* bank, int32_t storage, void* ws,
+                       size_t ws_bytes, const mdn_image* out, void* stream);
+
+/* Thread-local description of the last non-OK status (empty string if none). */
+const char* mdn_last_error(void);
+
+/* Library version string. */
+const char* mdn_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MDN_H */

@@ -1,0 +1,360 @@
+// Filter selection (Section 3, Eq. (3)-(6)) and adaptive filtering (Eq. (1), Eq. (9)-(10)).
+//
+// One 256-thread block owns a 16 x 64 tile of output pixels.
+//  1. The tile's input window plus a 3-pixel halo (clamped at the image border) is staged in
+//     LDS as float32 (RGB or grey).
+//  2. Selection, in float64: per position of the tile plus a 2-pixel halo, the central-difference
+//     gradients of every channel give A = sum_c gx^2, B = sum_c gx gy, C = sum_c gy^2 (evaluated at
+//     the clamped position, so the box reads replicated border values); a 5 x 5 box mean (a
+//     horizontal then a vertical 5-sum in LDS) gives the tensor (a, b, c); its eigen-features are
+//     binned into s(i). The orientation bin is found without atan2: the doubled-angle vector of
+//     the minor eigenvector, (c - a, -2b), is tested against the bin-boundary unit vectors with
+//     cross products.
+//  3. Filtering, in float32: the staged window is converted to YCbCr in place, the coarser level's
+//     window (for Eq. (9)) is staged too, and every pixel accumulates its bucket's f taps over the
+//     coarse window at floor(i/2) + j and g taps over the fine window at i + j, per channel. The
+//     result is written in YCbCr or converted back to RGB.
+
+#include "mdn_internal.h"
+
+#include <math.h>
+#include <string.h>
+
+namespace mdn {
+
+namespace {
+
+constexpr int kTW = 64;
+constexpr int kTH = 16;
+constexpr int kHalo = 3;                     // gradient (1) + box (2); also the max filter radius
+constexpr int kZW = kTW + 2 * kHalo;         // 70
+constexpr int kZH = kTH + 2 * kHalo;         // 22
+constexpr int kPW = kTW + 4;                 // tensor-product field: tile + 2-pixel halo
+constexpr int kPH = kTH + 4;
+
+struct FilterArgs {
+    ImageArg z;                 // RGB or grey input of this level
+    int32_t z_dtype;
+    ImageArg uc;                // coarser output (may be empty)
+    int32_t uc_dtype, uc_rgb;
+    const uint8_t* s_in;        // precomputed selector or null
+    int64_t s_pitch;
+    uint8_t* s_out;             // selector output or null
+    void* out;
+    int64_t out_row, out_plane;
+    int32_t out_dtype, out_rgb;
+    const void* coeffs;
+    int32_t K;
+    SelectArg sel;
+};
+
+__device__ __forceinline__ float load_any(const void* base, int32_t dtype, int64_t off) {
+    return dtype == MDN_F16 ? __half2float(static_cast<const __half*>(base)[off])
+                            : static_cast<const float*>(base)[off];
+}
+
+__device__ __forceinline__ void store_any(void* base, int32_t dtype, int64_t off, float v) {
+    if (dtype == MDN_F16)
+        static_cast<__half*>(base)[off] = __float2half_rn(v);
+    else
+        static_cast<float*>(base)[off] = v;
+}
+
+// Bucket index from the smoothed tensor (a, b, c), float64 throughout.
+__device__ __forceinline__ int bucket_of(double a, double b, double c, const SelectArg& sp) {
+    const double tr = a + c;
+    const double dd = a - c;
+    const double mu = sqrt(dd * dd + 4.0 * b * b);
+    const double l1 = 0.5 * (tr + mu);
+    const double l2 = fmax(0.5 * (tr - mu), 0.0);
+    const double s1 = sqrt(fmax(l1, 0.0));
+    const double s2 = sqrt(l2);
+    const double coh = (s1 + s2 > 0.0) ? (s1 - s2) / (s1 + s2) : 0.0;
+    // Orientation: the minor eigenvector's angle theta in [0, pi) doubled is the angle of
+    // (c - a, -2b) in [0, 2 pi); bin = floor(angle * q_theta / (2 pi)). An isotropic tensor has
+    // theta = pi/2 by convention.
+    const double X = c - a, Y = -2.0 * b;
+    int qt;
+    const int half = sp.q_theta >> 1;
+    if (X == 0.0 && Y == 0.0) {
+        qt = half;
+    } else {
+        const bool upper = (Y > 0.0) || (Y == 0.0 && X > 0.0);
+        const double px = upper ? X : -X, py = upper ? Y : -Y;
+        int k = 0;
+        for (int j = 0; j < half - 1; ++j) k += (sp.bcos[j] * py - sp.bsin[j] * px >= 0.0) ? 1 : 0;
+        qt = k + (upper ? 0 : half);
+    }
+    int qs = 0;
+    for (int j = 0; j < sp.q_s - 1; ++j) qs += (s1 >= sp.t_s[j]) ? 1 : 0;
+    int qc = 0;
+    for (int j = 0; j < sp.q_c - 1; ++j) qc += (coh >= sp.t_c[j]) ? 1 : 0;
+    return (qt * sp.q_s + qs) * sp.q_c + qc;
+}
+
+template <int C, int RF, int RG, typename TC, bool APPLY>
+__global__ __launch_bounds__(256) void k_select_apply(FilterArgs a) {
+    constexpr int kUH = kTH / 2 + 2 * (RF > 0 ? RF : 0);
+    constexpr int kUW = kTW / 2 + 2 * (RF > 0 ? RF : 0);
+    constexpr int kTF = RF >= 0 ? (2 * RF + 1) * (2 * RF + 1) : 0;
+    constexpr int kTG = (2 * RG + 1) * (2 * RG + 1);
+    constexpr int kD = kTF + kTG;
+
+    __shared__ float zs[C][kZH][kZW + 1];
+    __shared__ double pa[kPH][kPW], pb[kPH][kPW], pc[kPH][kPW];
+    __shared__ float us[C][RF >= 0 ? kUH : 1][RF >= 0 ? kUW + 1 : 1];
+
+    const int tid = threadIdx.x;
+    const int tx = tid & 63, ty = tid >> 6;
+    const int x0 = blockIdx.x * kTW, y0 = blockIdx.y * kTH;
+    const int W = a.z.w, H = a.z.h;
+
+    // 1. stage the input window (clamped)
+    for (int i = tid; i < C * kZH * kZW; i += 256) {
+        const int c = i / (kZH * kZW);
+        const int rem = i - c * kZH * kZW;
+        const int r = rem / kZW, q = rem - r * kZW;
+        const int gy = clampi(y0 - kHalo + r, 0, H - 1);
+        const int gx = clampi(x0 - kHalo + q, 0, W - 1);
+        zs[c][r][q] = load_any(a.z.data, a.z_dtype, (int64_t)c * a.z.plane + (int64_t)gy * a.z.row + gx);
+    }
+    __syncthreads();
+
+    // 2. selector
+    int sv[4];
+    if (a.s_in == nullptr) {
+        for (int i = tid; i < kPH * kPW; i += 256) {
+            const int r = i / kPW, q = i - r * kPW;
+            const int yc = clampi(y0 - 2 + r, 0, H - 1);
+            const int xc = clampi(x0 - 2 + q, 0, W - 1);
+            const int ly = yc - (y0 - kHalo), lx = xc - (x0 - kHalo);
+            const int lxr = clampi(xc + 1, 0, W - 1) - (x0 - kHalo);
+            const int lxl = clampi(xc - 1, 0, W - 1) - (x0 - kHalo);
+            const int lyd = clampi(yc + 1, 0, H - 1) - (y0 - kHalo);
+            const int lyu = clampi(yc - 1, 0, H - 1) - (y0 - kHalo);
+            double A = 0.0, B = 0.0, Cc = 0.0;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const double gx = ((double)zs[c][ly][lxr] - (double)zs[c][ly][lxl]) * 0.5;
+                const double gy = ((double)zs[c][lyd][lx] - (double)zs[c][lyu][lx]) * 0.5;
+                A += gx * gx;
+                B += gx * gy;
+                Cc += gy * gy;
+            }
+            pa[r][q] = A;
+            pb[r][q] = B;
+            pc[r][q] = Cc;
+        }
+        __syncthreads();
+        // horizontal 5-sums, written back in place (columns 0 .. kTW-1)
+        constexpr int kHN = (kPH * kTW + 255) / 256;
+        double ha[kHN], hb[kHN], hc[kHN];
+#pragma unroll
+        for (int k = 0; k < kHN; ++k) {
+            const int i = tid + k * 256;
+            if (i < kPH * kTW) {
+                const int r = i / kTW, q = i - r * kTW;
+                double sa = 0.0, sb = 0.0, sc = 0.0;
+#pragma unroll
+                for (int d = 0; d < 5; ++d) {
+                    sa += pa[r][q + d];
+                    sb += pb[r][q + d];
+                    sc += pc[r][q + d];
+                }
+                ha[k] = sa;
+                hb[k] = sb;
+                hc[k] = sc;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kHN; ++k) {
+            const int i = tid + k * 256;
+            if (i < kPH * kTW) {
+                const int r = i / kTW, q = i - r * kTW;
+                pa[r][q] = ha[k];
+                pb[r][q] = hb[k];
+                pc[r][q] = hc[k];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int py = ty + 4 * k;
+            double sa = 0.0, sb = 0.0, sc = 0.0;
+#pragma unroll
+            for (int d = 0; d < 5; ++d) {
+                sa += pa[py + d][tx];
+                sb += pb[py + d][tx];
+                sc += pc[py + d][tx];
+            }
+            sv[k] = bucket_of(sa / 25.0, sb / 25.0, sc / 25.0, a.sel);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int y = y0 + ty + 4 * k, x = x0 + tx;
+            sv[k] = (y < H && x < W) ? (int)a.s_in[(int64_t)y * a.s_pitch + x] : 0;
+        }
+    }
+    if (a.s_out != nullptr) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int y = y0 + ty + 4 * k, x = x0 + tx;
+            if (y < H && x < W) a.s_out[(int64_t)y * a.s_pitch + x] = (uint8_t)sv[k];
+        }
+    }
+    if constexpr (!APPLY) return;
+
+    // 3. filtering
+    __syncthreads();
+    if constexpr (C == 3) {
+        for (int i = tid; i < kZH * kZW; i += 256) {
+            const int r = i / kZW, q = i - r * kZW;
+            float yv, cb, cr;
+            Ycc::from_rgb(zs[0][r][q], zs[1][r][q], zs[2][r][q], yv, cb, cr);
+            zs[0][r][q] = yv;
+            zs[1][r][q] = cb;
+            zs[2][r][q] = cr;
+        }
+    }
+    if constexpr (RF >= 0) {
+        const int cy0 = y0 / 2 - RF, cx0 = x0 / 2 - RF;
+        for (int i = tid; i < kUH * kUW; i += 256) {
+            const int r = i / kUW, q = i - r * kUW;
+            const int gy = clampi(cy0 + r, 0, a.uc.h - 1);
+            const int gx = clampi(cx0 + q, 0, a.uc.w - 1);
+            const int64_t off = (int64_t)gy * a.uc.row + gx;
+            float v[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) v[c] = load_any(a.uc.data, a.uc_dtype, off + (int64_t)c * a.uc.plane);
+            if constexpr (C == 3) {
+                if (a.uc_rgb) Ycc::from_rgb(v[0], v[1], v[2], v[0], v[1], v[2]);
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) us[c][r][q] = v[c];
+        }
+    }
+    __syncthreads();
+
+    const TC* coef = static_cast<const TC*>(a.coeffs);
+#pragma unroll 1
+    for (int k = 0; k < 4; ++k) {
+        const int py = ty + 4 * k, px = tx;
+        const int y = y0 + py, x = x0 + px;
+        if (y >= H || x >= W) continue;
+        const int s = sv[k];
+        float acc[C];
+        if (s >= a.K) {
+#pragma unroll
+            for (int c = 0; c < C; ++c) acc[c] = __builtin_nanf("");
+        } else {
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const TC* h = coef + ((int64_t)s * C + c) * kD;
+                float sum = 0.0f;
+                if constexpr (RF >= 0) {
+                    const int uy = py / 2, ux = px / 2;
+#pragma unroll
+                    for (int dy = 0; dy < 2 * RF + 1; ++dy)
+#pragma unroll
+                        for (int dx = 0; dx < 2 * RF + 1; ++dx)
+                            sum += load_f(h + dy * (2 * RF + 1) + dx) * us[c][uy + dy][ux + dx];
+                }
+#pragma unroll
+                for (int dy = 0; dy < 2 * RG + 1; ++dy)
+#pragma unroll
+                    for (int dx = 0; dx < 2 * RG + 1; ++dx)
+                        sum += load_f(h + kTF + dy * (2 * RG + 1) + dx) *
+                               zs[c][py + kHalo - RG + dy][px + kHalo - RG + dx];
+                acc[c] = sum;
+            }
+        }
+        const int64_t off = (int64_t)y * a.out_row + x;
+        if constexpr (C == 3) {
+            if (a.out_rgb) Ycc::to_rgb(acc[0], acc[1], acc[2], acc[0], acc[1], acc[2]);
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) store_any(a.out, a.out_dtype, off + (int64_t)c * a.out_plane, acc[c]);
+    }
+}
+
+template <int C, int RF, int RG, typename TC>
+mdn_status launch_kernel(const FilterArgs& fa, bool apply, int w, int h, hipStream_t st) {
+    dim3 grid((w + kTW - 1) / kTW, (h + kTH - 1) / kTH);
+    if (apply)
+        k_select_apply<C, RF, RG, TC, true><<<grid, 256, 0, st>>>(fa);
+    else
+        k_select_apply<C, RF, RG, TC, false><<<grid, 256, 0, st>>>(fa);
+    return check_launch(apply ? "select_apply" : "select");
+}
+
+template <int C, typename TC>
+mdn_status dispatch_radii(const FilterArgs& fa, bool apply, int rf, int rg, int w, int h, hipStream_t st) {
+#define MDN_RADII(RF_, RG_) \
+    if (rf == RF_ && rg == RG_) return launch_kernel<C, RF_, RG_, TC>(fa, apply, w, h, st);
+    MDN_RADII(-1, 1)
+    MDN_RADII(-1, 2)
+    MDN_RADII(-1, 3)
+    MDN_RADII(1, 1)
+    MDN_RADII(2, 2)
+    MDN_RADII(3, 3)
+    MDN_RADII(2, 3)
+    MDN_RADII(1, 2)
+#undef MDN_RADII
+    return fail(MDN_ENOTSUP, "filter radii (f=%d, g=%d) not supported", rf, rg);
+}
+
+}  // namespace
+
+void fill_select_arg(const mdn_level& lvl, SelectArg& sa) {
+    memset(&sa, 0, sizeof(sa));
+    sa.q_theta = lvl.q_theta;
+    sa.q_s = lvl.q_s;
+    sa.q_c = lvl.q_c;
+    for (int j = 0; j < lvl.q_s - 1; ++j) sa.t_s[j] = lvl.t_s[j];
+    for (int j = 0; j < lvl.q_c - 1; ++j) sa.t_c[j] = lvl.t_c[j];
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int k = 1; k < lvl.q_theta / 2; ++k) {
+        const double ang = two_pi * (double)k / (double)lvl.q_theta;
+        sa.bcos[k - 1] = cos(ang);
+        sa.bsin[k - 1] = sin(ang);
+    }
+}
+
+mdn_status launch_select_apply(const mdn_image& z, const mdn_image* uc, const uint8_t* s_in, int64_t s_pitch,
+                               uint8_t* s_out, const mdn_level& lvl, const mdn_image* out, hipStream_t st) {
+    if (z.width == 0 || z.height == 0) return MDN_OK;
+    FilterArgs fa;
+    memset(&fa, 0, sizeof(fa));
+    fa.z = ImageArg{z.data, z.row_pitch, z.plane_pitch, z.width, z.height};
+    fa.z_dtype = z.dtype;
+    if (uc) {
+        fa.uc = ImageArg{uc->data, uc->row_pitch, uc->plane_pitch, uc->width, uc->height};
+        fa.uc_dtype = uc->dtype;
+        fa.uc_rgb = uc->color == MDN_RGB;
+    }
+    fa.s_in = s_in;
+    fa.s_pitch = s_pitch;
+    fa.s_out = s_out;
+    if (out) {
+        fa.out = out->data;
+        fa.out_row = out->row_pitch;
+        fa.out_plane = out->plane_pitch;
+        fa.out_dtype = out->dtype;
+        fa.out_rgb = out->color == MDN_RGB;
+    }
+    fa.coeffs = lvl.coeffs;
+    fa.K = lvl.q_theta * lvl.q_s * lvl.q_c;
+    fill_select_arg(lvl, fa.sel);
+    const bool apply = out != nullptr;
+    const int C = z.channels;
+    const int rf = lvl.radius_f < 0 ? -1 : lvl.radius_f;
+    if (C == 3 && lvl.coeff_dtype == MDN_F32) return dispatch_radii<3, float>(fa, apply, rf, lvl.radius_g, z.width, z.height, st);
+    if (C == 3 && lvl.coeff_dtype == MDN_F16) return dispatch_radii<3, __half>(fa, apply, rf, lvl.radius_g, z.width, z.height, st);
+    if (C == 1 && lvl.coeff_dtype == MDN_F32) return dispatch_radii<1, float>(fa, apply, rf, lvl.radius_g, z.width, z.height, st);
+    if (C == 1 && lvl.coeff_dtype == MDN_F16) return dispatch_radii<1, __half>(fa, apply, rf, lvl.radius_g, z.width, z.height, st);
+    return fail(MDN_EINVAL, "unsupported channels/coeff dtype");
+}
+
+}  // namespace mdn

@@ -1,0 +1,89 @@
+// Internal declarations shared by the HIP translation units of libmdn.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+#include "mdn.h"
+
+namespace mdn {
+
+// ------------------------------------------------------------------------ error state
+void set_error(const char* fmt, ...);
+mdn_status fail(mdn_status st, const char* fmt, ...);
+mdn_status check_launch(const char* what);
+
+// ------------------------------------------------------------------------ element access
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+template <typename T> __device__ __forceinline__ float load_f(const T* p);
+template <> __device__ __forceinline__ float load_f<float>(const float* p) { return *p; }
+template <> __device__ __forceinline__ float load_f<__half>(const __half* p) { return __half2float(*p); }
+
+template <typename T> __device__ __forceinline__ void store_f(T* p, float v);
+template <> __device__ __forceinline__ void store_f<float>(float* p, float v) { *p = v; }
+template <> __device__ __forceinline__ void store_f<__half>(__half* p, float v) { *p = __float2half_rn(v); }
+
+// float64 -> storage type with a single rounding (round to nearest even).
+template <typename T> __device__ __forceinline__ void store_d(T* p, double v);
+template <> __device__ __forceinline__ void store_d<float>(float* p, double v) { *p = (float)v; }
+template <> __device__ __forceinline__ void store_d<__half>(__half* p, double v) {
+    // Round to odd into float (24 bits >= 11 + 2), then float -> half rounds once correctly.
+    float t = __double2float_rz(v);
+    if ((double)t != v) t = __uint_as_float(__float_as_uint(t) | 1u);
+    *p = __float2half_rn(t);
+}
+
+// ------------------------------------------------------------------------ BT.601 full range
+// Y = Kr R + Kg G + Kb B, Cb = (B - Y) / (2 (1 - Kb)) + 1/2, Cr = (R - Y) / (2 (1 - Kr)) + 1/2.
+struct Ycc {
+    static constexpr float kr = 0.299f, kb = 0.114f, kg = 1.0f - 0.299f - 0.114f;
+    static constexpr float cb_s = 1.0f / 1.772f, cr_s = 1.0f / 1.402f;
+    __device__ __forceinline__ static void from_rgb(float r, float g, float b, float& y, float& cb, float& cr) {
+        y = 0.299f * r + 0.587f * g + 0.114f * b;
+        cb = (b - y) * (1.0f / 1.772f) + 0.5f;
+        cr = (r - y) * (1.0f / 1.402f) + 0.5f;
+    }
+    // Exact algebraic inverse: R = Y + 1.402 (Cr - 1/2), B = Y + 1.772 (Cb - 1/2),
+    // G = (Y - Kr R - Kb B) / Kg.
+    __device__ __forceinline__ static void to_rgb(float y, float cb, float cr, float& r, float& g, float& b) {
+        r = y + 1.402f * (cr - 0.5f);
+        b = y + 1.772f * (cb - 0.5f);
+        g = (y - 0.299f * r - 0.114f * b) * (1.0f / 0.587f);
+    }
+};
+
+// ------------------------------------------------------------------------ kernel parameters
+struct ImageArg {
+    const void* data;
+    int64_t row, plane;
+    int32_t w, h;
+};
+
+constexpr int kMaxThr = 16;       // max thresholds per feature (q_s, q_c <= 16)
+constexpr int kMaxTheta = 64;     // max orientation bins
+
+// Selector constants, passed by value.
+struct SelectArg {
+    int32_t q_theta, q_s, q_c;
+    int32_t pad;
+    double t_s[kMaxThr];
+    double t_c[kMaxThr];
+    // Unit vectors at the orientation-bin boundaries of the doubled angle, k = 1 .. q_theta/2 - 1,
+    // i.e. (cos(2 pi k / q_theta), sin(2 pi k / q_theta)).
+    double bcos[kMaxTheta / 2];
+    double bsin[kMaxTheta / 2];
+};
+
+void fill_select_arg(const mdn_level& lvl, SelectArg& a);
+
+// Launchers (stream work only; arguments already validated).
+mdn_status launch_down2(const mdn_image& in, const mdn_image& out, hipStream_t st);
+mdn_status launch_select_apply(const mdn_image& z, const mdn_image* uc, const uint8_t* s_in,
+                               int64_t s_pitch, uint8_t* s_out, const mdn_level& lvl,
+                               const mdn_image* out, hipStream_t st);
+
+int64_t elem_size(int32_t dtype);
+
+}  // namespace mdn
