@@ -197,3 +197,38 @@ def test_run_twice_bitwise_identical():
     a = M.denoise(zt, gb).cpu().numpy()
     b = M.denoise(zt, gb).cpu().numpy()
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("H,W", [(5, 9), (130, 97), (600, 808)])
+@pytest.mark.parametrize("coeff16", [False, True])
+def test_denoise_four_level_fp16_storage(H, W, coeff16):
+    """FP16 pyramid/outputs (FP32 accumulation): indices equal the oracle's in FP16-storage mode
+    except near boundaries; max-abs <= 2e-3 against it; PSNR within 0.01 dB of the pure FP64 oracle."""
+    import paper_1802_06130_amd as M
+    torch = _torch()
+    from mdn_testlib import TOL_F16
+    print(f"denoise 4-level fp16 {H}x{W} coeff16={coeff16}", flush=True)
+    bank = trained_bank_multiscale(levels=3)
+    z, u = synth.noisy_pair(4001 + H, H, W, 3, 25, dtype=np.float16)
+    gb = gpu_bank(bank, 3, coeff_dtype=torch.float16 if coeff16 else torch.float32)
+    out = _host(M.denoise(_dev(z), gb, storage=M.F16))
+    ref16 = O.denoise(z, bank, storage=np.float16)
+    # per-level index parity on the FP16 pyramid (bit-identical on both sides)
+    L = 3
+    pyr_g = M.pyramid_build(_dev(z), L, storage=torch.float16)
+    pyr_o = O.build_pyramid(z, L + 1, storage=np.float16)
+    mask = np.zeros(pyr_o[L - 1].shape[1:], bool)
+    for lev in range(L - 1, -1, -1):
+        zg = _dev(z) if lev == 0 else pyr_g[lev - 1]
+        s = M.select_filters(zg, gb.levels[lev]).cpu().numpy()
+        mism, _, _ = index_parity(s, pyr_o[lev], bank.levels[lev])
+        if lev < L - 1:
+            mask = propagate_mask(mask, mism.shape, bank.levels[lev].radius_f)
+        mask = mask | mism
+    err = max_abs(out, ref16, mask)
+    ref64 = O.denoise(z, bank)
+    dpsnr = abs(O.psnr(out, u) - O.psnr(ref64, u))
+    print(f"  max-abs vs fp16-mode oracle {err:.3g}, |dPSNR| vs fp64 oracle {dpsnr:.4f} dB")
+    assert err <= TOL_F16
+    if H * W > 10000:
+        assert dpsnr <= 0.01
