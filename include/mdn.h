@@ -130,6 +130,83 @@ mdn_status mdn_denoise_workspace_size(int32_t width, int32_t height, int32_t cha
 mdn_status mdn_denoise(const mdn_image* in, const mdn_bank* bank, int32_t storage, void* ws,
                        size_t ws_bytes, const mdn_image* out, void* stream);
 
+/* ---------------------------------------------------------------------------------------
+ * Training (Eq. (7)-(8)): one least-squares regression per bucket (and per YCbCr channel,
+ * footnote of Section 3), level by level from the second-coarsest level down (Section 4).
+ * --------------------------------------------------------------------------------------- */
+
+/* Regression vector layouts.
+ * MDN_X_PER_CHANNEL:   x_i = [R_{i/2} u^{l+1}_c ; R_i z^l_c] per channel c (Eq. (10)), target u^l_{i,c};
+ *                      K*channels systems of D = taps_f + taps_g unknowns and one right-hand side.
+ * MDN_X_CROSS_CHANNEL: x_i = [R_i z_Y ; R_i z_Cb ; R_i z_Cr] (g taps of all channels, no upscale
+ *                      block), targets u_Y, u_Cb, u_Cr; K systems of D = 3 taps_g unknowns and 3
+ *                      right-hand sides. Used for the precision study only. */
+typedef enum { MDN_X_PER_CHANNEL = 0, MDN_X_CROSS_CHANNEL = 1 } mdn_x_layout;
+
+/* Products used for the normal-equation accumulation (FP32 accumulators on MFMA; each call's
+ * per-bucket sums are then added into float64 accumulators).
+ * MDN_GRAM_F32:    FP32 products (v_mfma_f32_32x32x2_f32).
+ * MDN_GRAM_BF16X3: BF16 products on a hi/lo split, x*y ~ hi hi + hi lo + lo hi (v_mfma_f32_32x32x16_bf16). */
+typedef enum { MDN_GRAM_F32 = 0, MDN_GRAM_BF16X3 = 1 } mdn_gram_precision;
+
+/* Normal equations of one level, caller-owned device memory (float64 / int64):
+ * G [systems][D][D], b [systems][nrhs][D], yy [systems][nrhs], n [K] (samples per bucket).
+ * System index: k*channels + c (per channel) or k (cross channel). Sizes: mdn_gram_dims. */
+typedef struct {
+    int32_t  K;          /* buckets (<= 255) */
+    int32_t  channels;   /* 1 or 3 */
+    int32_t  layout;     /* mdn_x_layout */
+    int32_t  radius_f;   /* -1 (single scale) or 1..3; must be -1 for the cross layout */
+    int32_t  radius_g;   /* 1..3 */
+    int32_t  reserved;   /* must be 0 */
+    double*  G;
+    double*  b;
+    int64_t* n;
+    double*  yy;
+} mdn_gram;
+
+/* D (unknowns per system), nrhs and number of systems of a gram configuration. */
+mdn_status mdn_gram_dims(const mdn_gram* g, int32_t* D, int32_t* nrhs, int32_t* systems);
+
+/* Zero the accumulators (enqueued on stream). */
+mdn_status mdn_gram_zero(const mdn_gram* g, void* stream);
+
+/* Bytes of workspace mdn_train_accumulate needs for a width x height level. */
+mdn_status mdn_train_workspace_size(int32_t width, int32_t height, int32_t channels, size_t* bytes);
+
+/* Add one training pair's samples at one level to the normal equations (Eq. (8)):
+ * z:        noisy level z^l (RGB or grey); selects s(i) with `sel` (thresholds; coefficients unused);
+ * u_coarse: coarser output u^{l+1} (YCbCr, or RGB for the coarsest pyramid level), NULL for the
+ *           single-scale or cross-channel layouts;
+ * target:   clean level u^l (RGB or grey), same size as z.
+ * Samples are taken in raster order, so repeated calls are bitwise reproducible. */
+mdn_status mdn_train_accumulate(const mdn_gram* g, const mdn_image* z, const mdn_image* u_coarse,
+                                const mdn_image* target, const mdn_level* sel, int32_t precision,
+                                void* ws, size_t ws_bytes, void* stream);
+
+/* Bytes of workspace mdn_train_solve needs. */
+mdn_status mdn_train_solve_workspace_size(const mdn_gram* g, size_t* bytes);
+
+/* Solve every system: h = (G/n + lambda I)^{-1} b/n by Cholesky in float64 (ridge reading of the
+ * regression; the paper defers its details to BLADE). Buckets with n < min_count, or whose
+ * factorisation fails, take the pooled solution of the level (sums of G, b, n over all buckets);
+ * *n_fallback (device int32, accumulated with atomics, zero it first) counts those systems.
+ * coeffs: device [K][channels][D], written in coeff_dtype (MDN_F32 or MDN_F16, rounded once).
+ * Enqueued on stream. */
+mdn_status mdn_train_solve(const mdn_gram* g, double lambda, int64_t min_count, void* coeffs,
+                           int32_t coeff_dtype, int32_t* n_fallback, void* ws, size_t ws_bytes,
+                           void* stream);
+
+/* Per-pixel strength sqrt(lambda1) and coherence of z's structure tensor (as used by the
+ * selector), float64, dense [height][width] device arrays. */
+mdn_status mdn_level_features(const mdn_image* z, double* strength, double* coherence, void* stream);
+
+/* Equal-population thresholds: the k/q quantiles (k = 1..q-1, linear interpolation between order
+ * statistics) of n device doubles, written to out_host[q-1]. Synchronises `stream`. */
+mdn_status mdn_quantiles_workspace_size(int64_t n, size_t* bytes);
+mdn_status mdn_quantiles(const double* values, int64_t n, int32_t q, double* out_host, void* ws,
+                         size_t ws_bytes, void* stream);
+
 /* Thread-local description of the last non-OK status (empty string if none). */
 const char* mdn_last_error(void);
 

@@ -224,3 +224,197 @@ def denoise(img, bank: Bank, storage: int = F32, ws=None, out=None):
     _check(lib().mdn_denoise(ct.byref(image(img)), ct.byref(b), storage, ct.c_void_p(ws.data_ptr()),
                              ws.numel(), ct.byref(image(out)), _stream_ptr()))
     return out
+
+
+# ----------------------------------------------------------------------------- training
+
+X_PER_CHANNEL, X_CROSS_CHANNEL = 0, 1
+GRAM_F32, GRAM_BF16X3 = 0, 1
+
+
+class MdnGram(ct.Structure):
+    _fields_ = [("K", ct.c_int32), ("channels", ct.c_int32), ("layout", ct.c_int32), ("radius_f", ct.c_int32),
+                ("radius_g", ct.c_int32), ("reserved", ct.c_int32), ("G", ct.c_void_p), ("b", ct.c_void_p),
+                ("n", ct.c_void_p), ("yy", ct.c_void_p)]
+
+
+def _train_sigs(L):
+    vp, i32, i64 = ct.c_void_p, ct.c_int32, ct.c_int64
+    P = ct.POINTER
+    sig = {
+        "mdn_gram_dims": [P(MdnGram), P(i32), P(i32), P(i32)],
+        "mdn_gram_zero": [P(MdnGram), vp],
+        "mdn_train_workspace_size": [i32, i32, i32, P(ct.c_size_t)],
+        "mdn_train_accumulate": [P(MdnGram), P(MdnImage), P(MdnImage), P(MdnImage), P(MdnLevel), i32, vp,
+                                 ct.c_size_t, vp],
+        "mdn_train_solve_workspace_size": [P(MdnGram), P(ct.c_size_t)],
+        "mdn_train_solve": [P(MdnGram), ct.c_double, i64, vp, i32, vp, vp, ct.c_size_t, vp],
+        "mdn_level_features": [P(MdnImage), vp, vp, vp],
+        "mdn_quantiles_workspace_size": [i64, P(ct.c_size_t)],
+        "mdn_quantiles": [vp, i64, i32, P(ct.c_double), vp, ct.c_size_t, vp],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = ct.c_int
+
+
+class Gram:
+    """Normal equations of one level (device float64 accumulators)."""
+
+    def __init__(self, K: int, channels: int, radius_g: int, radius_f: Optional[int] = None,
+                 layout: int = X_PER_CHANNEL, device="cuda"):
+        torch = _torch()
+        _train_sigs(lib())
+        self.cfg = (int(K), int(channels), int(layout), -1 if radius_f is None else int(radius_f), int(radius_g))
+        d = MdnGram(*self.cfg, 0, None, None, None, None)
+        D, nrhs, nsys = ct.c_int32(), ct.c_int32(), ct.c_int32()
+        _check(lib().mdn_gram_dims(ct.byref(d), ct.byref(D), ct.byref(nrhs), ct.byref(nsys)))
+        self.D, self.nrhs, self.systems = D.value, nrhs.value, nsys.value
+        self.G = torch.zeros(self.systems * self.D * self.D, dtype=torch.float64, device=device)
+        self.b = torch.zeros(self.systems * self.nrhs * self.D, dtype=torch.float64, device=device)
+        self.n = torch.zeros(K, dtype=torch.int64, device=device)
+        self.yy = torch.zeros(self.systems * self.nrhs, dtype=torch.float64, device=device)
+
+    def desc(self) -> MdnGram:
+        return MdnGram(*self.cfg, 0, ct.c_void_p(self.G.data_ptr()), ct.c_void_p(self.b.data_ptr()),
+                       ct.c_void_p(self.n.data_ptr()), ct.c_void_p(self.yy.data_ptr()))
+
+    def zero(self):
+        _check(lib().mdn_gram_zero(ct.byref(self.desc()), _stream_ptr()))
+
+
+def _ws(nbytes, device):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def train_accumulate(gram: Gram, z, target, level: Level, u_coarse=None, precision: int = GRAM_F32,
+                     coarse_color=None, ws=None):
+    C, H, W = z.shape
+    _train_sigs(lib())
+    need = ct.c_size_t()
+    _check(lib().mdn_train_workspace_size(W, H, C, ct.byref(need)))
+    if ws is None or ws.numel() < need.value:
+        ws = _ws(need.value, z.device)
+    uc = None
+    if u_coarse is not None:
+        uc = image(u_coarse, GRAY if C == 1 else (coarse_color if coarse_color is not None else YCC))
+    lv = level.desc()
+    _check(lib().mdn_train_accumulate(ct.byref(gram.desc()), ct.byref(image(z)),
+                                      ct.byref(uc) if uc is not None else None, ct.byref(image(target)),
+                                      ct.byref(lv), precision, ct.c_void_p(ws.data_ptr()), ws.numel(),
+                                      _stream_ptr()))
+    return ws
+
+
+def train_solve(gram: Gram, lam: float, min_count: Optional[int] = None, coeff_dtype=None):
+    """Solve every system; returns (coeffs [K][C][D] device tensor, number of fallback systems)."""
+    torch = _torch()
+    dev = gram.G.device
+    dt = coeff_dtype or torch.float32
+    K, C = gram.cfg[0], gram.cfg[1]
+    out = torch.empty((K, C, gram.D), dtype=dt, device=dev)
+    nfb = torch.zeros(1, dtype=torch.int32, device=dev)
+    need = ct.c_size_t()
+    _check(lib().mdn_train_solve_workspace_size(ct.byref(gram.desc()), ct.byref(need)))
+    ws = _ws(need.value, dev)
+    mc = gram.D if min_count is None else int(min_count)
+    _check(lib().mdn_train_solve(ct.byref(gram.desc()), float(lam), mc, ct.c_void_p(out.data_ptr()),
+                                 _dtype_code(out), ct.c_void_p(nfb.data_ptr()), ct.c_void_p(ws.data_ptr()),
+                                 ws.numel(), _stream_ptr()))
+    return out, int(nfb.item())
+
+
+def level_features(z):
+    """(strength, coherence) float64 device tensors [H][W] of the RGB/grey image z."""
+    torch = _torch()
+    _train_sigs(lib())
+    C, H, W = z.shape
+    st = torch.empty((H, W), dtype=torch.float64, device=z.device)
+    co = torch.empty((H, W), dtype=torch.float64, device=z.device)
+    _check(lib().mdn_level_features(ct.byref(image(z)), ct.c_void_p(st.data_ptr()), ct.c_void_p(co.data_ptr()),
+                                    _stream_ptr()))
+    return st, co
+
+
+def quantiles(values, q: int) -> np.ndarray:
+    """k/q quantiles (k = 1..q-1) of a float64 device tensor, computed by the library."""
+    _train_sigs(lib())
+    v = values.contiguous().view(-1)
+    n = v.numel()
+    need = ct.c_size_t()
+    _check(lib().mdn_quantiles_workspace_size(n, ct.byref(need)))
+    ws = _ws(need.value, v.device)
+    out = (ct.c_double * (q - 1))()
+    _check(lib().mdn_quantiles(ct.c_void_p(v.data_ptr()), n, q, out, ct.c_void_p(ws.data_ptr()), ws.numel(),
+                               _stream_ptr()))
+    return np.array(list(out))
+
+
+def level_thresholds(zs, q_s: int, q_c: int):
+    """Equal-population strength / coherence thresholds over the given level images."""
+    torch = _torch()
+    feats = [level_features(z) for z in zs]
+    st = torch.cat([f[0].view(-1) for f in feats])
+    co = torch.cat([f[1].view(-1) for f in feats])
+    t_s = quantiles(st, q_s) if q_s > 1 else np.zeros(0)
+    t_c = quantiles(co, q_c) if q_c > 1 else np.zeros(0)
+    return t_s, t_c
+
+
+def train_single(pairs, q_theta: int, q_s: int, q_c: int, radius: int, lam: float, thresholds=None,
+                 precision: int = GRAM_F32, coeff_dtype=None, min_count=None):
+    """Single-scale bank (Eq. (1), (7)-(8)) from (noisy, clean) (C, H, W) device tensors."""
+    torch = _torch()
+    C = pairs[0][0].shape[0]
+    if thresholds is None:
+        t_s, t_c = level_thresholds([z for z, _ in pairs], q_s, q_c)
+    else:
+        t_s, t_c = thresholds
+    K = q_theta * (len(t_s) + 1) * (len(t_c) + 1)
+    dummy = torch.zeros((K, C, (2 * radius + 1) ** 2), dtype=torch.float32, device=pairs[0][0].device)
+    sel = Level(q_theta, t_s, t_c, radius, None, dummy, C)
+    g = Gram(K, C, radius, None, device=pairs[0][0].device)
+    ws = None
+    for z, u in pairs:
+        ws = train_accumulate(g, z, u, sel, precision=precision, ws=ws)
+    co, nfb = train_solve(g, lam, min_count, coeff_dtype)
+    return Bank([Level(q_theta, t_s, t_c, radius, None, co, C)]), g, nfb
+
+
+def train_multiscale(pairs, n_trained_levels: int, q_theta: int, q_s: int, q_c: int, radius_f: int,
+                     radius_g: int, lam: float, thresholds=None, precision: int = GRAM_F32, coeff_dtype=None,
+                     min_count=None, storage=None):
+    """Multiscale bank trained from the second-coarsest level down (Section 4); pairs are
+    (noisy, clean) (C, H, W) device tensors. Returns (Bank, grams, fallback counts)."""
+    torch = _torch()
+    L = n_trained_levels
+    C = pairs[0][0].shape[0]
+    dev = pairs[0][0].device
+    pz = [[z] + pyramid_build(z, L, storage=storage) for z, _ in pairs]
+    pu = [[u] + pyramid_build(u, L, storage=storage) for _, u in pairs]
+    levels: List[Optional[Level]] = [None] * L
+    grams, fbs = [None] * L, [None] * L
+    uhat = [p[L] for p in pz]
+    coarse_color = GRAY if C == 1 else RGB
+    D = (2 * radius_f + 1) ** 2 + (2 * radius_g + 1) ** 2
+    ws = None
+    for lev in range(L - 1, -1, -1):
+        if thresholds is not None:
+            t_s, t_c = thresholds[lev]
+        else:
+            t_s, t_c = level_thresholds([p[lev] for p in pz], q_s, q_c)
+        K = q_theta * (len(t_s) + 1) * (len(t_c) + 1)
+        sel = Level(q_theta, t_s, t_c, radius_g, radius_f, torch.zeros((K, C, D), dtype=torch.float32, device=dev), C)
+        g = Gram(K, C, radius_g, radius_f, device=dev)
+        for i in range(len(pairs)):
+            ws = train_accumulate(g, pz[i][lev], pu[i][lev], sel, u_coarse=uhat[i], precision=precision,
+                                  coarse_color=coarse_color, ws=ws)
+        co, nfb = train_solve(g, lam, min_count, coeff_dtype)
+        lvl = Level(q_theta, t_s, t_c, radius_g, radius_f, co, C)
+        levels[lev], grams[lev], fbs[lev] = lvl, g, nfb
+        uhat = [apply_level(pz[i][lev], lvl, u_coarse=uhat[i], coarse_color=coarse_color,
+                            out_dtype=pz[i][lev].dtype) for i in range(len(pairs))]
+        coarse_color = GRAY if C == 1 else YCC
+    return Bank(levels), grams, fbs

@@ -103,6 +103,23 @@ size_t image_bytes(int w, int h, int c, int dtype) {
     return align256((size_t)pitch_for(w) * (size_t)h * (size_t)c * (size_t)elem_size(dtype));
 }
 
+
+mdn_status check_gram(const mdn_gram* g) {
+    if (!g) return fail(MDN_EINVAL, "gram: null");
+    if (g->reserved != 0) return fail(MDN_EINVAL, "gram: reserved field must be 0");
+    if (g->K < 1 || g->K > 255) return fail(MDN_EINVAL, "gram: K must be 1..255");
+    if (g->channels != 1 && g->channels != 3) return fail(MDN_EINVAL, "gram: channels must be 1 or 3");
+    if (g->layout != MDN_X_PER_CHANNEL && g->layout != MDN_X_CROSS_CHANNEL) return fail(MDN_EINVAL, "gram: layout");
+    if (g->radius_g < 1 || g->radius_g > 3) return fail(MDN_ENOTSUP, "gram: radius_g must be 1..3");
+    if (!(g->radius_f == -1 || (g->radius_f >= 1 && g->radius_f <= 3))) return fail(MDN_ENOTSUP, "gram: radius_f");
+    if (g->layout == MDN_X_CROSS_CHANNEL && g->radius_f != -1) return fail(MDN_EINVAL, "gram: cross layout has no upscale block");
+    int D, nrhs, spk;
+    gram_dims(*g, &D, &nrhs, &spk);
+    if (D + nrhs > kMaxFeat) return fail(MDN_ENOTSUP, "gram: %d features exceed %d", D + nrhs, kMaxFeat);
+    if (!g->G || !g->b || !g->n || !g->yy) return fail(MDN_EINVAL, "gram: null accumulator");
+    return MDN_OK;
+}
+
 }  // namespace
 }  // namespace mdn
 
@@ -254,6 +271,119 @@ mdn_status mdn_denoise(const mdn_image* in, const mdn_bank* bank, int32_t storag
         coarse = dst;
     }
     return MDN_OK;
+}
+
+
+mdn_status mdn_gram_dims(const mdn_gram* g, int32_t* D, int32_t* nrhs, int32_t* systems) {
+    g_err[0] = 0;
+    mdn_status st = check_gram(g);
+    if (st && st != MDN_EINVAL) return st;
+    if (!g) return st;
+    if (!D || !nrhs || !systems) return fail(MDN_EINVAL, "null output");
+    int d, r, spk;
+    gram_dims(*g, &d, &r, &spk);
+    *D = d;
+    *nrhs = r;
+    *systems = g->K * spk;
+    return MDN_OK;
+}
+
+mdn_status mdn_gram_zero(const mdn_gram* g, void* stream) {
+    g_err[0] = 0;
+    mdn_status st = check_gram(g);
+    if (st) return st;
+    return gram_zero(*g, static_cast<hipStream_t>(stream));
+}
+
+mdn_status mdn_train_workspace_size(int32_t width, int32_t height, int32_t channels, size_t* bytes) {
+    g_err[0] = 0;
+    if (!bytes) return fail(MDN_EINVAL, "null bytes");
+    if (width < 0 || height < 0) return fail(MDN_EINVAL, "negative size");
+    if (channels != 1 && channels != 3) return fail(MDN_EINVAL, "channels must be 1 or 3");
+    *bytes = train_ws_bytes(width, height, channels);
+    return MDN_OK;
+}
+
+mdn_status mdn_train_accumulate(const mdn_gram* g, const mdn_image* z, const mdn_image* u_coarse,
+                                const mdn_image* target, const mdn_level* sel, int32_t precision, void* ws,
+                                size_t ws_bytes, void* stream) {
+    g_err[0] = 0;
+    mdn_status st = check_gram(g);
+    if (st) return st;
+    if ((st = check_image(z, "z"))) return st;
+    if (z->color == MDN_YCC) return fail(MDN_EINVAL, "z: pass RGB or grey");
+    if ((st = check_image(target, "target"))) return st;
+    if (target->width != z->width || target->height != z->height || target->channels != z->channels ||
+        target->color == MDN_YCC)
+        return fail(MDN_EINVAL, "target must match z (RGB or grey)");
+    if (z->channels != g->channels) return fail(MDN_EINVAL, "gram channels differ from the image's");
+    if ((st = check_level(sel, z->channels))) return st;
+    if (sel->q_theta * sel->q_s * sel->q_c != g->K) return fail(MDN_EINVAL, "selector K differs from gram K");
+    if (precision != MDN_GRAM_F32 && precision != MDN_GRAM_BF16X3) return fail(MDN_EINVAL, "unknown precision");
+    if (g->radius_f >= 1) {
+        if ((st = check_image(u_coarse, "u_coarse"))) return st;
+        if (u_coarse->width != half_up(z->width) || u_coarse->height != half_up(z->height) ||
+            u_coarse->channels != z->channels)
+            return fail(MDN_EINVAL, "u_coarse must be ceil(w/2) x ceil(h/2) with the same channels");
+    } else if (u_coarse) {
+        return fail(MDN_EINVAL, "u_coarse given for a layout without upscale block");
+    }
+    if (empty(*z)) return MDN_OK;
+    if (!ws || ws_bytes < train_ws_bytes(z->width, z->height, z->channels))
+        return fail(MDN_ENOMEM, "workspace too small (need %zu)", train_ws_bytes(z->width, z->height, z->channels));
+    if (((uintptr_t)ws) & 255) return fail(MDN_EINVAL, "workspace must be 256-byte aligned");
+    return train_accumulate(*g, *z, g->radius_f >= 1 ? u_coarse : nullptr, *target, *sel, precision, ws,
+                            static_cast<hipStream_t>(stream));
+}
+
+mdn_status mdn_train_solve_workspace_size(const mdn_gram* g, size_t* bytes) {
+    g_err[0] = 0;
+    mdn_status st = check_gram(g);
+    if (st) return st;
+    if (!bytes) return fail(MDN_EINVAL, "null bytes");
+    *bytes = solve_ws_bytes(*g);
+    return MDN_OK;
+}
+
+mdn_status mdn_train_solve(const mdn_gram* g, double lambda, int64_t min_count, void* coeffs, int32_t coeff_dtype,
+                           int32_t* n_fallback, void* ws, size_t ws_bytes, void* stream) {
+    g_err[0] = 0;
+    mdn_status st = check_gram(g);
+    if (st) return st;
+    if (!(lambda >= 0.0)) return fail(MDN_EINVAL, "lambda must be >= 0");
+    if (!coeffs) return fail(MDN_EINVAL, "null coeffs");
+    if (coeff_dtype != MDN_F32 && coeff_dtype != MDN_F16) return fail(MDN_EINVAL, "unknown coeff dtype");
+    if (!ws || ws_bytes < solve_ws_bytes(*g)) return fail(MDN_ENOMEM, "workspace too small (need %zu)", solve_ws_bytes(*g));
+    if (((uintptr_t)ws) & 255) return fail(MDN_EINVAL, "workspace must be 256-byte aligned");
+    return train_solve(*g, lambda, min_count, coeffs, coeff_dtype, n_fallback, ws, static_cast<hipStream_t>(stream));
+}
+
+mdn_status mdn_level_features(const mdn_image* z, double* strength, double* coherence, void* stream) {
+    g_err[0] = 0;
+    mdn_status st = check_image(z, "z");
+    if (st) return st;
+    if (z->color == MDN_YCC) return fail(MDN_EINVAL, "z: pass RGB or grey");
+    if (empty(*z)) return MDN_OK;
+    if (!strength || !coherence) return fail(MDN_EINVAL, "null output");
+    return launch_features(*z, strength, coherence, static_cast<hipStream_t>(stream));
+}
+
+mdn_status mdn_quantiles_workspace_size(int64_t n, size_t* bytes) {
+    g_err[0] = 0;
+    if (!bytes) return fail(MDN_EINVAL, "null bytes");
+    if (n < 1 || n > 2000000000LL) return fail(MDN_EINVAL, "n must be 1..2e9");
+    *bytes = quantile_ws_bytes(n);
+    return MDN_OK;
+}
+
+mdn_status mdn_quantiles(const double* values, int64_t n, int32_t q, double* out_host, void* ws, size_t ws_bytes,
+                         void* stream) {
+    g_err[0] = 0;
+    if (!values || !out_host) return fail(MDN_EINVAL, "null pointer");
+    if (n < 1 || n > 2000000000LL) return fail(MDN_EINVAL, "n must be 1..2e9");
+    if (q < 2 || q > 64) return fail(MDN_EINVAL, "q must be 2..64");
+    if (!ws || ws_bytes < quantile_ws_bytes(n)) return fail(MDN_ENOMEM, "workspace too small");
+    return quantiles(values, n, q, out_host, ws, ws_bytes, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

@@ -45,6 +45,8 @@ struct FilterArgs {
     int32_t out_dtype, out_rgb;
     const void* coeffs;
     int32_t K;
+    double* feat_s;             // features mode: strength and coherence per pixel (row pitch W)
+    double* feat_c;
     SelectArg sel;
 };
 
@@ -60,16 +62,23 @@ __device__ __forceinline__ void store_any(void* base, int32_t dtype, int64_t off
         static_cast<float*>(base)[off] = v;
 }
 
-// Bucket index from the smoothed tensor (a, b, c), float64 throughout.
-__device__ __forceinline__ int bucket_of(double a, double b, double c, const SelectArg& sp) {
+// Strength sqrt(lambda1) and coherence (sqrt(l1) - sqrt(l2)) / (sqrt(l1) + sqrt(l2)) of the
+// smoothed tensor [[a, b], [b, c]], float64.
+__device__ __forceinline__ void strength_coherence(double a, double b, double c, double& s1, double& coh) {
     const double tr = a + c;
     const double dd = a - c;
     const double mu = sqrt(dd * dd + 4.0 * b * b);
     const double l1 = 0.5 * (tr + mu);
     const double l2 = fmax(0.5 * (tr - mu), 0.0);
-    const double s1 = sqrt(fmax(l1, 0.0));
+    s1 = sqrt(fmax(l1, 0.0));
     const double s2 = sqrt(l2);
-    const double coh = (s1 + s2 > 0.0) ? (s1 - s2) / (s1 + s2) : 0.0;
+    coh = (s1 + s2 > 0.0) ? (s1 - s2) / (s1 + s2) : 0.0;
+}
+
+// Bucket index from the smoothed tensor (a, b, c), float64 throughout.
+__device__ __forceinline__ int bucket_of(double a, double b, double c, const SelectArg& sp) {
+    double s1, coh;
+    strength_coherence(a, b, c, s1, coh);
     // Orientation: the minor eigenvector's angle theta in [0, pi) doubled is the angle of
     // (c - a, -2b) in [0, 2 pi); bin = floor(angle * q_theta / (2 pi)). An isotropic tensor has
     // theta = pi/2 by convention.
@@ -92,8 +101,10 @@ __device__ __forceinline__ int bucket_of(double a, double b, double c, const Sel
     return (qt * sp.q_s + qs) * sp.q_c + qc;
 }
 
-template <int C, int RF, int RG, typename TC, bool APPLY>
+// MODE 0: selector only; 1: selector + filtering; 2: strength/coherence features only.
+template <int C, int RF, int RG, typename TC, int MODE>
 __global__ __launch_bounds__(256) void k_select_apply(FilterArgs a) {
+    constexpr bool APPLY = MODE == 1;
     constexpr int kUH = kTH / 2 + 2 * (RF > 0 ? RF : 0);
     constexpr int kUW = kTW / 2 + 2 * (RF > 0 ? RF : 0);
     constexpr int kTF = RF >= 0 ? (2 * RF + 1) * (2 * RF + 1) : 0;
@@ -188,7 +199,18 @@ __global__ __launch_bounds__(256) void k_select_apply(FilterArgs a) {
                 sb += pb[py + d][tx];
                 sc += pc[py + d][tx];
             }
-            sv[k] = bucket_of(sa / 25.0, sb / 25.0, sc / 25.0, a.sel);
+            if constexpr (MODE == 2) {
+                const int y = y0 + py, x = x0 + tx;
+                if (y < H && x < W) {
+                    double s1, coh;
+                    strength_coherence(sa / 25.0, sb / 25.0, sc / 25.0, s1, coh);
+                    a.feat_s[(int64_t)y * W + x] = s1;
+                    a.feat_c[(int64_t)y * W + x] = coh;
+                }
+                sv[k] = 0;
+            } else {
+                sv[k] = bucket_of(sa / 25.0, sb / 25.0, sc / 25.0, a.sel);
+            }
         }
     } else {
 #pragma unroll
@@ -283,9 +305,9 @@ template <int C, int RF, int RG, typename TC>
 mdn_status launch_kernel(const FilterArgs& fa, bool apply, int w, int h, hipStream_t st) {
     dim3 grid((w + kTW - 1) / kTW, (h + kTH - 1) / kTH);
     if (apply)
-        k_select_apply<C, RF, RG, TC, true><<<grid, 256, 0, st>>>(fa);
+        k_select_apply<C, RF, RG, TC, 1><<<grid, 256, 0, st>>>(fa);
     else
-        k_select_apply<C, RF, RG, TC, false><<<grid, 256, 0, st>>>(fa);
+        k_select_apply<C, RF, RG, TC, 0><<<grid, 256, 0, st>>>(fa);
     return check_launch(apply ? "select_apply" : "select");
 }
 
@@ -306,6 +328,25 @@ mdn_status dispatch_radii(const FilterArgs& fa, bool apply, int rf, int rg, int 
 }
 
 }  // namespace
+
+mdn_status launch_features(const mdn_image& z, double* strength, double* coherence, hipStream_t st) {
+    if (z.width == 0 || z.height == 0) return MDN_OK;
+    FilterArgs fa;
+    memset(&fa, 0, sizeof(fa));
+    fa.z = ImageArg{z.data, z.row_pitch, z.plane_pitch, z.width, z.height};
+    fa.z_dtype = z.dtype;
+    fa.feat_s = strength;
+    fa.feat_c = coherence;
+    fa.sel.q_theta = 2;
+    fa.sel.q_s = 1;
+    fa.sel.q_c = 1;
+    dim3 grid((z.width + kTW - 1) / kTW, (z.height + kTH - 1) / kTH);
+    if (z.channels == 3)
+        k_select_apply<3, -1, 1, float, 2><<<grid, 256, 0, st>>>(fa);
+    else
+        k_select_apply<1, -1, 1, float, 2><<<grid, 256, 0, st>>>(fa);
+    return check_launch("features");
+}
 
 void fill_select_arg(const mdn_level& lvl, SelectArg& sa) {
     memset(&sa, 0, sizeof(sa));

@@ -63,6 +63,7 @@ struct ImageArg {
 
 constexpr int kMaxThr = 16;       // max thresholds per feature (q_s, q_c <= 16)
 constexpr int kMaxTheta = 64;     // max orientation bins
+constexpr int kMaxFeat = 160;     // max regression features incl. targets (training)
 
 // Selector constants, passed by value.
 struct SelectArg {
@@ -83,6 +84,21 @@ mdn_status launch_down2(const mdn_image& in, const mdn_image& out, hipStream_t s
 mdn_status launch_select_apply(const mdn_image& z, const mdn_image* uc, const uint8_t* s_in,
                                int64_t s_pitch, uint8_t* s_out, const mdn_level& lvl,
                                const mdn_image* out, hipStream_t st);
+
+mdn_status launch_features(const mdn_image& z, double* strength, double* coherence, hipStream_t st);
+
+// training
+int gram_dims(const mdn_gram& g, int* D, int* nrhs, int* sys_per_k);
+mdn_status gram_zero(const mdn_gram& g, hipStream_t st);
+size_t train_ws_bytes(int w, int h, int C);
+mdn_status train_accumulate(const mdn_gram& g, const mdn_image& z, const mdn_image* uc, const mdn_image& target,
+                            const mdn_level& sel, int precision, void* ws, hipStream_t st);
+size_t solve_ws_bytes(const mdn_gram& g);
+mdn_status train_solve(const mdn_gram& g, double lam, int64_t min_count, void* coeffs, int out_dtype,
+                       int32_t* n_fallback, void* ws, hipStream_t st);
+size_t quantile_ws_bytes(int64_t n);
+mdn_status quantiles(const double* values, int64_t n, int q, double* out_host, void* ws, size_t ws_bytes,
+                     hipStream_t st);
 
 int64_t elem_size(int32_t dtype);
 
