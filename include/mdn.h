@@ -113,10 +113,13 @@ mdn_status mdn_select_filters(const mdn_image* z, const mdn_level* lvl, uint8_t*
  * u_coarse: the coarser level's output (YCbCr, or RGB for the coarsest pyramid level, which
  *           is converted), size ceil(w/2) x ceil(h/2); NULL iff lvl->radius_f < 0.
  * s:        precomputed selector (device uint8 [height][s_pitch]) or NULL to select inline.
- * u_out:    output, YCbCr (intermediate levels) or RGB (converted back), or grey. */
+ * u_out:    output, YCbCr (intermediate levels) or RGB (converted back), or grey.
+ * s_out:    NULL, or device uint8 [height][s_pitch] that receives the selector used (inline mode).
+ * Float16 coefficients of 7x7/7x7 colour levels run the column-walk kernel in float16 arithmetic
+ * with float32 accumulation; float32 coefficients keep float32 arithmetic throughout. */
 mdn_status mdn_apply_level(const mdn_image* z, const mdn_image* u_coarse, const uint8_t* s,
                            int64_t s_pitch, const mdn_level* lvl, const mdn_image* u_out,
-                           void* stream);
+                           uint8_t* s_out, void* stream);
 
 /* Bytes of device workspace mdn_denoise needs for a width x height image with `channels`
  * channels, a bank of `levels` trained levels and pyramid storage dtype `storage`. */

@@ -63,7 +63,7 @@ def lib() -> ct.CDLL:
         sig = {
             "mdn_pyramid_build": [P(MdnImage), i32, P(MdnImage), vp],
             "mdn_select_filters": [P(MdnImage), P(MdnLevel), vp, i64, vp],
-            "mdn_apply_level": [P(MdnImage), P(MdnImage), vp, i64, P(MdnLevel), P(MdnImage), vp],
+            "mdn_apply_level": [P(MdnImage), P(MdnImage), vp, i64, P(MdnLevel), P(MdnImage), vp, vp],
             "mdn_denoise_workspace_size": [i32, i32, i32, i32, i32, P(ct.c_size_t)],
             "mdn_denoise": [P(MdnImage), P(MdnBank), i32, vp, ct.c_size_t, P(MdnImage), vp],
         }
@@ -186,8 +186,9 @@ def select_filters(z, level: Level, out=None):
 
 
 def apply_level(z, level: Level, u_coarse=None, s=None, out=None, out_color=None, coarse_color=None,
-                out_dtype=None):
-    """One filtering step; returns u_out (C, H, W) in YCbCr unless out_color says otherwise."""
+                out_dtype=None, s_out=None):
+    """One filtering step; returns u_out (C, H, W) in YCbCr unless out_color says otherwise.
+    ``s_out`` (uint8 (H, W) tensor) receives the selector used when selecting inline."""
     torch = _torch()
     C, H, W = z.shape
     if out_color is None:
@@ -198,10 +199,13 @@ def apply_level(z, level: Level, u_coarse=None, s=None, out=None, out_color=None
     if u_coarse is not None:
         uc = image(u_coarse, coarse_color if coarse_color is not None else (GRAY if C == 1 else YCC))
     lv = level.desc()
+    if s is None and s_out is None and u_coarse is not None and level.coeffs.dtype == torch.float16 and C == 3:
+        s_out = torch.empty((H, W), dtype=torch.uint8, device=z.device)   # the float16 path's selector map
+    sp = s.stride(0) if s is not None else (s_out.stride(0) if s_out is not None else 0)
     _check(lib().mdn_apply_level(ct.byref(image(z)), ct.byref(uc) if uc is not None else None,
-                                 ct.c_void_p(s.data_ptr()) if s is not None else None,
-                                 s.stride(0) if s is not None else 0, ct.byref(lv),
-                                 ct.byref(image(out, out_color)), _stream_ptr()))
+                                 ct.c_void_p(s.data_ptr()) if s is not None else None, sp, ct.byref(lv),
+                                 ct.byref(image(out, out_color)),
+                                 ct.c_void_p(s_out.data_ptr()) if s_out is not None else None, _stream_ptr()))
     return out
 
 

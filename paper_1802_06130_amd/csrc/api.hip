@@ -171,7 +171,7 @@ mdn_status mdn_select_filters(const mdn_image* z, const mdn_level* lvl, uint8_t*
 }
 
 mdn_status mdn_apply_level(const mdn_image* z, const mdn_image* u_coarse, const uint8_t* s, int64_t s_pitch,
-                           const mdn_level* lvl, const mdn_image* u_out, void* stream) {
+                           const mdn_level* lvl, const mdn_image* u_out, uint8_t* s_out, void* stream) {
     g_err[0] = 0;
     mdn_status st = check_image(z, "z");
     if (st) return st;
@@ -189,8 +189,9 @@ mdn_status mdn_apply_level(const mdn_image* z, const mdn_image* u_coarse, const 
         return fail(MDN_EINVAL, "u_coarse given for a single-scale level");
     }
     if (empty(*z)) return MDN_OK;
-    if (s && s_pitch < z->width) return fail(MDN_EINVAL, "s_pitch < width");
-    return launch_select_apply(*z, lvl->radius_f >= 1 ? u_coarse : nullptr, s, s_pitch, nullptr, *lvl, u_out,
+    if ((s || s_out) && s_pitch < z->width) return fail(MDN_EINVAL, "s_pitch < width");
+    if (s && s_out) return fail(MDN_EINVAL, "give either a selector or a selector output, not both");
+    return launch_select_apply(*z, lvl->radius_f >= 1 ? u_coarse : nullptr, s, s_pitch, s_out, *lvl, u_out,
                                static_cast<hipStream_t>(stream));
 }
 
@@ -210,6 +211,7 @@ mdn_status mdn_denoise_workspace_size(int32_t width, int32_t height, int32_t cha
         total += image_bytes(w, h, channels, storage);                 // z^l
         if (l < levels) total += image_bytes(w, h, channels, storage); // u^l
     }
+    total += align256((size_t)width * (size_t)height);                  // selector map (largest level)
     *bytes = total;
     return MDN_OK;
 }
@@ -260,6 +262,7 @@ mdn_status mdn_denoise(const mdn_image* in, const mdn_bank* bank, int32_t storag
             p += image_bytes(w, h, C, storage);
         }
     }
+    uint8_t* smap = reinterpret_cast<uint8_t*>(p);
     zl[0] = *in;
     for (int l = 1; l <= L; ++l)
         if ((st = launch_down2(zl[l - 1], zl[l], s))) return st;
@@ -267,7 +270,10 @@ mdn_status mdn_denoise(const mdn_image* in, const mdn_bank* bank, int32_t storag
     const mdn_image* coarse = &zl[L];
     for (int l = L - 1; l >= 0; --l) {
         const mdn_image* dst = l == 0 ? out : &ul[l];
-        if ((st = launch_select_apply(zl[l], coarse, nullptr, 0, nullptr, bank->level[l], dst, s))) return st;
+        const bool walk = bank->level[l].coeff_dtype == MDN_F16 && walk_supported(bank->level[l], C);
+        if ((st = launch_select_apply(zl[l], coarse, nullptr, zl[l].width, walk ? smap : nullptr, bank->level[l], dst,
+                                      s)))
+            return st;
         coarse = dst;
     }
     return MDN_OK;

@@ -85,6 +85,9 @@ mdn_status launch_select_apply(const mdn_image& z, const mdn_image* uc, const ui
                                int64_t s_pitch, uint8_t* s_out, const mdn_level& lvl,
                                const mdn_image* out, hipStream_t st);
 
+bool walk_supported(const mdn_level& lvl, int channels);
+mdn_status launch_walk(const mdn_image& z, const mdn_image& uc, const mdn_level& lvl, const mdn_image& out,
+                       const uint8_t* s_in, uint8_t* s_buf, int64_t s_pitch, hipStream_t st);
 mdn_status launch_features(const mdn_image& z, double* strength, double* coherence, hipStream_t st);
 
 // training

@@ -1,0 +1,374 @@
+// Persistent column-walk filtering kernel for the multiscale step (Eq. (9)) with 7x7 upscale and
+// 7x7 denoise filters on colour images, float16 filter coefficients resident in LDS and float32
+// accumulation. The selector s(i) comes from the float64 selection pass as a uint8 map.
+//
+// Work decomposition. A wavefront owns a strip of 58 output columns and 56 output rows; its 64
+// lanes hold the columns x0-3 .. x0+60 (a 3-column halo on each side) and walk down the strip one
+// output row per step. Persistent 512-thread workgroups (one per CU, two waves per SIMD; the bank
+// fills 145 KB of the 160 KB LDS) take strips round-robin from a list that may span many images.
+//
+// Per step (output row y) every lane
+//  - converts the prefetched RGB pixel (y+3, x) to YCbCr and float16 and forms the new row of the
+//    7x7 fine window, the neighbouring columns coming from DPP wave shifts (wave_shl / wave_shr)
+//    instead of LDS, and prefetches row y+4 and s(y+1);
+//  - after odd rows, adds a row to the 7x7 window of the coarser output around floor(x/2), built
+//    from three loads per lane (columns floor(x/2) - 3, floor(x/2), floor(x/2) + 3) and DPP shifts
+//    by two lanes;
+//  - accumulates, per channel, 14 coefficient rows of its bucket (one ds_read_b128 each: 7 taps
+//    and a zero as float16 pairs) against the window pairs with v_dot2_f32_f16.
+// Window rows live in fixed register slots (row r in slot r mod 7); the 14-row step body is
+// expanded at compile time, so no register ever moves when the windows slide.
+
+#include "mdn_internal.h"
+
+#include <string.h>
+
+#include <type_traits>
+#include <utility>
+
+#ifndef MDN_WALK_WAVES
+#define MDN_WALK_WAVES 4
+#endif
+
+namespace mdn {
+
+namespace {
+
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+
+constexpr int kLanesOut = 58;          // output columns per wave
+constexpr int kStripRows = 56;         // output rows per strip (multiple of 14, even)
+constexpr int kWaves = MDN_WALK_WAVES;  // waves per workgroup
+constexpr int kRows = 14;              // coefficient rows per (bucket, channel): 7 f + 7 g
+constexpr int kRowBytes = 16;          // 8 halves per row (7 taps + 0)
+constexpr int kBucketBytes = 3 * kRows * kRowBytes;   // 672
+constexpr int kMaxK = 160 * 1024 / kBucketBytes;      // 243 buckets fit in LDS
+
+__device__ __forceinline__ uint32_t shl1(uint32_t v) { return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130, 0xF, 0xF, false); }
+__device__ __forceinline__ uint32_t shr1(uint32_t v) { return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138, 0xF, 0xF, false); }
+__device__ __forceinline__ float shl1f(float v) { return __uint_as_float(shl1(__float_as_uint(v))); }
+__device__ __forceinline__ float shr1f(float v) { return __uint_as_float(shr1(__float_as_uint(v))); }
+__device__ __forceinline__ uint32_t pack2(float lo, float hi) {
+    const _Float16 a = (_Float16)lo, b = (_Float16)hi;
+    return (uint32_t)__builtin_bit_cast(unsigned short, a) | ((uint32_t)__builtin_bit_cast(unsigned short, b) << 16);
+}
+__device__ __forceinline__ float dot2(uint32_t c, uint32_t w, float acc) {
+    return __builtin_amdgcn_fdot2(__builtin_bit_cast(h2, c), __builtin_bit_cast(h2, w), acc, false);
+}
+
+// One image of the strip list.
+struct WalkImage {
+    const void* z;          // RGB input of the level
+    const void* uc;         // coarser output (YCbCr, or RGB at the coarsest level)
+    void* out;
+    int64_t z_row, z_plane, uc_row, uc_plane, o_row, o_plane;
+    int32_t W, H, Wc, Hc;
+    int32_t z_dtype, uc_dtype, uc_rgb, o_dtype, o_rgb;
+    int32_t nsx;            // strips across
+    int32_t strip_begin;    // first strip index of this image in the list
+    int32_t pad;
+    const uint8_t* s_map;   // selector of this level (from the selection pass)
+    int64_t s_pitch;
+};
+
+struct WalkArgs {
+    WalkImage single;           // used when imgs == nullptr
+    const WalkImage* imgs;      // device array (batch) or null
+    int32_t n_imgs, n_strips;
+    const void* coeffs;         // [K][3][98], float16 or float32
+    int32_t coeff_dtype, K;
+};
+
+__device__ __forceinline__ float ld(const void* p, int dtype, int64_t off) {
+    return dtype == MDN_F16 ? (float)static_cast<const _Float16*>(p)[off] : static_cast<const float*>(p)[off];
+}
+__device__ __forceinline__ void st(void* p, int dtype, int64_t off, float v) {
+    if (dtype == MDN_F16)
+        static_cast<_Float16*>(p)[off] = (_Float16)v;
+    else
+        static_cast<float*>(p)[off] = v;
+}
+
+template <int I>
+using IC = std::integral_constant<int, I>;
+
+template <typename F, int... Is>
+__device__ __forceinline__ void unroll(F&& f, std::integer_sequence<int, Is...>) {
+    (f(IC<Is>{}), ...);
+}
+
+template <typename T> __device__ __forceinline__ float ldt(const void* p, int64_t off) {
+    return (float)static_cast<const T*>(p)[off];
+}
+template <typename T> __device__ __forceinline__ void stt(void* p, int64_t off, float v) {
+    static_cast<T*>(p)[off] = (T)v;
+}
+
+// Filtering pass of the column walk (the selector map comes from the selection pass).
+// TZ: input storage, TU: coarser-output storage, TO: output storage.
+template <typename TZ, typename TU, typename TO>
+__global__ __launch_bounds__(64 * MDN_WALK_WAVES) void k_walk(WalkArgs a) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char bank[];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+
+    // ---- bank into LDS: row (k, c, r) = 7 taps + 0, float16
+    {
+        const int nrows = a.K * 3 * kRows;
+        for (int i = tid; i < nrows; i += 64 * kWaves) {
+            const int k = i / (3 * kRows);
+            const int rem = i - k * 3 * kRows;
+            const int c = rem / kRows, r = rem - c * kRows;
+            const int64_t base = ((int64_t)k * 3 + c) * 98 + r * 7;
+            float v[7];
+            for (int t = 0; t < 7; ++t) v[t] = ld(a.coeffs, a.coeff_dtype, base + t);
+            // the 7th tap meets the shared pair (x+3 of Y | x+3 of Cb) for Y and Cb, (x+3 of Cr | 0) for Cr
+            u4 q;
+            q.x = pack2(v[0], v[1]);
+            q.y = pack2(v[2], v[3]);
+            q.z = pack2(v[4], v[5]);
+            q.w = c == 1 ? pack2(0.0f, v[6]) : pack2(v[6], 0.0f);
+            *reinterpret_cast<u4*>(bank + (size_t)i * kRowBytes) = q;
+        }
+    }
+    __syncthreads();
+
+    for (int strip = blockIdx.x * kWaves + wave; strip < a.n_strips; strip += gridDim.x * kWaves) {
+        WalkImage im;
+        if (a.imgs == nullptr) {
+            im = a.single;
+        } else {
+            int lo = 0, hi = a.n_imgs - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (a.imgs[mid].strip_begin <= strip) lo = mid; else hi = mid - 1;
+            }
+            im = a.imgs[lo];
+        }
+        const int local = strip - im.strip_begin;
+        const int sy = local / im.nsx, sx = local - sy * im.nsx;
+        const int W = im.W, H = im.H;
+        const int xs = sx * kLanesOut, ys = sy * kStripRows;
+        const int x = xs - 3 + lane;
+        const int xc = clampi(x, 0, W - 1);
+        const bool out_lane = lane >= 3 && lane < 3 + kLanesOut && x < W;
+        const int cxq = x >> 1;
+        // element offsets fit in 32 bits (validated on the host); bases stay wave-uniform
+        const TZ* zb = static_cast<const TZ*>(im.z);
+        const uint32_t zpl = (uint32_t)im.z_plane, zrow = (uint32_t)im.z_row;
+        const TU* ub = static_cast<const TU*>(im.uc);
+        const uint32_t upl = (uint32_t)im.uc_plane, urow = (uint32_t)im.uc_row;
+        const uint32_t uc0 = clampi(cxq - 3, 0, im.Wc - 1), uc1 = clampi(cxq, 0, im.Wc - 1),
+                       uc2 = clampi(cxq + 3, 0, im.Wc - 1);
+        const uint8_t* sb = im.s_map;
+        const uint32_t spitch = (uint32_t)im.s_pitch;
+
+        auto load_rgb = [&](int row, float v[3]) {
+            const uint32_t o = (uint32_t)clampi(row, 0, H - 1) * zrow + (uint32_t)xc;
+            v[0] = (float)zb[o];
+            v[1] = (float)zb[o + zpl];
+            v[2] = (float)zb[o + 2 * zpl];
+        };
+        // a window row: w[c][0..2] = pairs (x-3,x-2) (x-1,x) (x+1,x+2) of channel c,
+        // w[0][3] = (Y(x+3), Cb(x+3)) and w[2][3] = (Cr(x+3), 0) shared by the three channels
+        auto fine_row = [&](const float rgb[3], uint32_t w[3][4]) {
+            float yv, cb, cr;
+            Ycc::from_rgb(rgb[0], rgb[1], rgb[2], yv, cb, cr);
+            const float v[3] = {yv, cb, cr};
+            float p3[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const float p1 = shl1f(v[c]), p2 = shl1f(p1);
+                p3[c] = shl1f(p2);
+                const float m1 = shr1f(v[c]), m2 = shr1f(m1), m3 = shr1f(m2);
+                w[c][0] = pack2(m3, m2);
+                w[c][1] = pack2(m1, v[c]);
+                w[c][2] = pack2(p1, p2);
+            }
+            w[0][3] = pack2(p3[0], p3[1]);
+            w[2][3] = pack2(p3[2], 0.0f);
+        };
+        auto load_coarse = [&](int cr, float u[3][3]) {
+            const uint32_t r0 = (uint32_t)clampi(cr, 0, im.Hc - 1) * urow;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                u[0][c] = (float)ub[r0 + c * upl + uc0];
+                u[1][c] = (float)ub[r0 + c * upl + uc1];
+                u[2][c] = (float)ub[r0 + c * upl + uc2];
+            }
+        };
+        auto coarse_row = [&](float u[3][3], uint32_t w[3][4]) {
+            if (im.uc_rgb) {
+#pragma unroll
+                for (int j = 0; j < 3; ++j) Ycc::from_rgb(u[j][0], u[j][1], u[j][2], u[j][0], u[j][1], u[j][2]);
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const float dm2 = shl1f(shl1f(u[0][c]));      // floor(x/2) - 2 (from lane x+2)
+                const float dp1 = shl1f(shl1f(u[1][c]));      // floor(x/2) + 1
+                const float dm1 = shr1f(shr1f(u[1][c]));      // floor(x/2) - 1 (from lane x-2)
+                const float dp2 = shr1f(shr1f(u[2][c]));      // floor(x/2) + 2
+                w[c][0] = pack2(u[0][c], dm2);
+                w[c][1] = pack2(dm1, u[1][c]);
+                w[c][2] = pack2(dp1, dp2);
+            }
+            w[0][3] = pack2(u[2][0], u[2][1]);
+            w[2][3] = pack2(u[2][2], 0.0f);
+        };
+
+        // ring slots: fine row r sits in fw[r mod 7], coarse row cr in cw[cr mod 7] (ys = 0 mod 14)
+        uint32_t fw[7][3][4];
+        uint32_t cw[7][3][4];
+        float znext[3];
+        int snext;
+        {
+            float t[3];
+#pragma unroll
+            for (int d = -3; d <= 2; ++d) {
+                load_rgb(ys + d, t);
+                fine_row(t, fw[(d + 7) % 7]);
+            }
+            const int cy = ys >> 1;
+#pragma unroll
+            for (int d = -3; d <= 3; ++d) {
+                float u[3][3];
+                load_coarse(cy + d, u);
+                coarse_row(u, cw[(d + 7) % 7]);
+            }
+            load_rgb(ys + 3, znext);
+            snext = sb[(uint32_t)clampi(ys, 0, H - 1) * spitch + (uint32_t)xc];
+        }
+        for (int y0 = ys; y0 < ys + kStripRows; y0 += 14) {
+            unroll([&](auto ic) {
+                constexpr int I = decltype(ic)::value;
+                const int y = y0 + I;
+                // the prefetched row y+3 enters the fine window; prefetch row y+4 and s(y+1)
+                fine_row(znext, fw[(I + 3) % 7]);
+                const int s = snext;
+                load_rgb(y + 4, znext);
+                snext = sb[(uint32_t)clampi(y + 1, 0, H - 1) * spitch + (uint32_t)xc];
+                float unext[3][3];
+                if constexpr (I & 1) load_coarse(((y + 1) >> 1) + 3, unext);
+                const uint8_t* bp = bank + (size_t)s * kBucketBytes;
+                float acc[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    float af = 0.0f, ag = 0.0f;
+#pragma unroll
+                    for (int r = 0; r < 7; ++r) {
+                        const u4 q = *reinterpret_cast<const u4*>(bp + (c * kRows + r) * kRowBytes);
+                        const uint32_t (*w)[4] = cw[(I / 2 + r + 4) % 7];
+                        af = dot2(q.x, w[c][0], af);
+                        af = dot2(q.y, w[c][1], af);
+                        af = dot2(q.z, w[c][2], af);
+                        af = dot2(q.w, w[c == 2 ? 2 : 0][3], af);
+                    }
+#pragma unroll
+                    for (int r = 0; r < 7; ++r) {
+                        const u4 q = *reinterpret_cast<const u4*>(bp + (c * kRows + 7 + r) * kRowBytes);
+                        const uint32_t (*w)[4] = fw[(I + r + 4) % 7];
+                        ag = dot2(q.x, w[c][0], ag);
+                        ag = dot2(q.y, w[c][1], ag);
+                        ag = dot2(q.z, w[c][2], ag);
+                        ag = dot2(q.w, w[c == 2 ? 2 : 0][3], ag);
+                    }
+                    acc[c] = af + ag;
+                }
+                if (out_lane && y < H) {
+                    if (im.o_rgb) Ycc::to_rgb(acc[0], acc[1], acc[2], acc[0], acc[1], acc[2]);
+                    const uint32_t off = (uint32_t)y * (uint32_t)im.o_row + (uint32_t)x;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) stt<TO>(im.out, off + c * (uint32_t)im.o_plane, acc[c]);
+                }
+                // after an odd row the next row has a new floor(y/2): the coarse row floor/2 + 3 enters
+                if constexpr (I & 1) coarse_row(unext, cw[((I + 1) / 2 + 3) % 7]);
+            }, std::make_integer_sequence<int, 14>{});
+        }
+    }
+}
+
+}  // namespace
+
+bool walk_supported(const mdn_level& lvl, int channels) {
+    return channels == 3 && lvl.radius_f == 3 && lvl.radius_g == 3 && lvl.q_theta * lvl.q_s * lvl.q_c <= kMaxK;
+}
+
+size_t walk_lds_bytes(int K) { return (size_t)K * kBucketBytes; }
+
+static void fill_walk_image(WalkImage& wi, const mdn_image& z, const mdn_image& uc, const mdn_image& out, int begin) {
+    memset(&wi, 0, sizeof(wi));
+    wi.z = z.data;
+    wi.uc = uc.data;
+    wi.out = out.data;
+    wi.z_row = z.row_pitch;
+    wi.z_plane = z.plane_pitch;
+    wi.uc_row = uc.row_pitch;
+    wi.uc_plane = uc.plane_pitch;
+    wi.o_row = out.row_pitch;
+    wi.o_plane = out.plane_pitch;
+    wi.W = z.width;
+    wi.H = z.height;
+    wi.Wc = uc.width;
+    wi.Hc = uc.height;
+    wi.z_dtype = z.dtype;
+    wi.uc_dtype = uc.dtype;
+    wi.uc_rgb = uc.color == MDN_RGB;
+    wi.o_dtype = out.dtype;
+    wi.o_rgb = out.color == MDN_RGB;
+    wi.nsx = (z.width + kLanesOut - 1) / kLanesOut;
+    wi.strip_begin = begin;
+}
+
+int walk_strips(int w, int h) {
+    return ((w + kLanesOut - 1) / kLanesOut) * ((h + kStripRows - 1) / kStripRows);
+}
+
+template <typename TZ, typename TU, typename TO>
+static mdn_status launch_typed_walk(const WalkArgs& a, int grid, size_t lds, hipStream_t st) {
+    static int attr_done = 0;
+    if (!attr_done) {
+        if (hipFuncSetAttribute((const void*)k_walk<TZ, TU, TO>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                160 * 1024) != hipSuccess)
+            return fail(MDN_EDEVICE, "walk: cannot reserve LDS");
+        attr_done = 1;
+    }
+    k_walk<TZ, TU, TO><<<grid, 64 * kWaves, lds, st>>>(a);
+    return check_launch("walk");
+}
+
+// Selection pass (float64 tensor, uint8 map) followed by the filtering pass.
+mdn_status launch_walk(const mdn_image& z, const mdn_image& uc, const mdn_level& lvl, const mdn_image& out,
+                       const uint8_t* s_in, uint8_t* s_buf, int64_t s_pitch, hipStream_t st) {
+    if (z.width == 0 || z.height == 0) return MDN_OK;
+    mdn_status e;
+    const uint8_t* smap = s_in;
+    if (!smap) {
+        if ((e = launch_select_apply(z, nullptr, nullptr, s_pitch, s_buf, lvl, nullptr, st))) return e;
+        smap = s_buf;
+    }
+    WalkArgs a;
+    memset(&a, 0, sizeof(a));
+    fill_walk_image(a.single, z, uc, out, 0);
+    a.single.s_map = smap;
+    a.single.s_pitch = s_pitch;
+    a.imgs = nullptr;
+    a.n_imgs = 1;
+    a.n_strips = walk_strips(z.width, z.height);
+    a.coeffs = lvl.coeffs;
+    a.coeff_dtype = lvl.coeff_dtype;
+    a.K = lvl.q_theta * lvl.q_s * lvl.q_c;
+    const size_t lds = walk_lds_bytes(a.K);
+    int dev = 0, ncu = 256;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    const int blocks = (a.n_strips + kWaves - 1) / kWaves;
+    const int grid = blocks < ncu ? blocks : ncu;
+    const bool zh = z.dtype == MDN_F16, uh = uc.dtype == MDN_F16, oh = out.dtype == MDN_F16;
+    if (zh && uh && oh) return launch_typed_walk<_Float16, _Float16, _Float16>(a, grid, lds, st);
+    if (!zh && uh && !oh) return launch_typed_walk<float, _Float16, float>(a, grid, lds, st);
+    if (!zh && !uh && !oh) return launch_typed_walk<float, float, float>(a, grid, lds, st);
+    if (zh && !uh && oh) return launch_typed_walk<_Float16, float, _Float16>(a, grid, lds, st);
+    return fail(MDN_ENOTSUP, "walk: input/coarse/output dtype combination not supported");
+}
+
+}  // namespace mdn

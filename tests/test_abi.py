@@ -33,8 +33,8 @@ def test_version_string():
 
 def test_workspace_size_host_only():
     n = M.denoise_workspace_size(1024, 768, 3, 2, M.F32)
-    # z^1, u^1 (512 x 384) and z^2 (256 x 192), pitches rounded up to 64 elements
-    want = 3 * 4 * (512 * 384 * 2 + 256 * 192)
+    # z^1, u^1 (512 x 384) and z^2 (256 x 192), pitches rounded up to 64 elements, + selector map
+    want = 3 * 4 * (512 * 384 * 2 + 256 * 192) + 1024 * 768
     assert n == want
     assert M.denoise_workspace_size(0, 0, 3, 3, M.F16) == 0
     with pytest.raises(M.MdnError):
@@ -93,7 +93,7 @@ def test_pyramid_rejects_wrong_level_size():
 def test_apply_requires_coarse_for_multiscale():
     z = _img(data=0x1000)
     out = _img(data=0x2000, color=M.YCC)
-    st = M.lib().mdn_apply_level(ct.byref(z), None, None, 0, ct.byref(_level()), ct.byref(out), None)
+    st = M.lib().mdn_apply_level(ct.byref(z), None, None, 0, ct.byref(_level()), ct.byref(out), None, None)
     assert st == B.MDN_EINVAL and b"u_coarse" in M.lib().mdn_last_error()
 
 

@@ -232,3 +232,38 @@ def test_denoise_four_level_fp16_storage(H, W, coeff16):
     assert err <= TOL_F16
     if H * W > 10000:
         assert dpsnr <= 0.01
+
+
+@pytest.mark.parametrize("H,W", [(1, 1), (2, 3), (57, 59), (113, 175), (200, 116), (57, 1)])
+def test_walk_kernel_fp16_bank_sizes(H, W):
+    """The float16-bank kernel (column walk, strips of 58 columns x 56 rows) across strip edges."""
+    import paper_1802_06130_amd as M
+    torch = _torch()
+    from mdn_testlib import TOL_F16
+    print(f"walk fp16 {H}x{W}", flush=True)
+    bank = trained_bank_multiscale(levels=2)
+    for in_dt in (np.float16, np.float32):
+        z, u = synth.noisy_pair(5001 + H + W, H, W, 3, 25, dtype=in_dt)
+        gb = gpu_bank(bank, 3, coeff_dtype=torch.float16)
+        st = M.F16 if in_dt == np.float16 else M.F32
+        out = _host(M.denoise(_dev(z), gb, storage=st))
+        ref = O.denoise(z, bank, storage=in_dt)
+        L = 2
+        pyr_g = M.pyramid_build(_dev(z), L)
+        pyr_o = O.build_pyramid(z, L + 1, storage=in_dt)
+        mask = np.zeros(pyr_o[L - 1].shape[1:], bool)
+        for lev in range(L - 1, -1, -1):
+            zg = _dev(z) if lev == 0 else pyr_g[lev - 1]
+            s = M.select_filters(zg, gb.levels[lev]).cpu().numpy()
+            mism, _, _ = index_parity(s, pyr_o[lev], bank.levels[lev])
+            if lev < L - 1:
+                mask = propagate_mask(mask, mism.shape, bank.levels[lev].radius_f)
+            mask = mask | mism
+        err = max_abs(out, ref, mask)
+        print(f"  input {np.dtype(in_dt).name}: max-abs {err:.3g}")
+        assert err <= TOL_F16
+        # the selector the walk kernel itself used, level 0
+        s_walk = torch.zeros((H, W), dtype=torch.uint8, device="cuda")
+        uc = M.apply_level(pyr_g[0], gb.levels[1], u_coarse=pyr_g[1], coarse_color=M.RGB)
+        M.apply_level(_dev(z), gb.levels[0], u_coarse=uc, out_color=M.RGB, s_out=s_walk)
+        index_parity(s_walk.cpu().numpy(), pyr_o[0], bank.levels[0])
