@@ -366,6 +366,8 @@ void fill_select_arg(const mdn_level& lvl, SelectArg& sa) {
 mdn_status launch_select_apply(const mdn_image& z, const mdn_image* uc, const uint8_t* s_in, int64_t s_pitch,
                                uint8_t* s_out, const mdn_level& lvl, const mdn_image* out, hipStream_t st) {
     if (z.width == 0 || z.height == 0) return MDN_OK;
+    // selector only: column-walk float64 selection pass
+    if (!out && s_out && !s_in) return launch_select_walk(z, lvl, s_out, s_pitch, st);
     // float16 filter banks of 7x7/7x7 colour filters run on the persistent column-walk kernel
     if (out && uc && lvl.coeff_dtype == MDN_F16 && walk_supported(lvl, z.channels)) {
         if (!s_in && !s_out) return fail(MDN_EINVAL, "float16 levels need a selector map (s) or a buffer for it (s_out)");

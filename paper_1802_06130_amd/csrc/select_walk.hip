@@ -1,0 +1,295 @@
+// Column-walk selection pass (Section 3, Eq. (3)-(6)): bucket index s(i) of every pixel of an RGB
+// level, written as a uint8 map for the filtering pass.
+//
+// A wavefront owns 58 output columns (64 lanes with a 3-column halo each side) and walks down a
+// strip of rows. For each new row r = y+2 it forms, per lane and in float64, the differences
+// dx = z(r, x+1) - z(r, x-1) (neighbouring columns from DPP wave shifts) and dy = z(r+1, x) -
+// z(r-1, x), accumulates A = sum_c dx^2, B = sum_c dx dy, C = sum_c dy^2 (four times the products
+// of the central-difference gradients: the factor is exact), replaces positions outside the image
+// by the value at the clamped position (readlane), and sums 5 neighbouring lanes (DPP on the two
+// halves of each double). A 5-row ring then gives the 5 x 5 box sums of row y, 100 times the box
+// mean (a, b, c). The bucket needs no square root or division:
+//   strength:  sqrt(lambda1) >= t  <=>  lambda1 >= t^2  <=>  mu >= 2 t^2 - tr      (mu^2 = (a-c)^2 + 4b^2)
+//   coherence: (sqrt(l1)-sqrt(l2))/(sqrt(l1)+sqrt(l2)) >= t  <=>  mu >= (2t / (1 + t^2)) tr   (tr > 0)
+//   orientation: the doubled-angle vector of the minor eigenvector, (c - a, -2b), against the bin
+//   boundary directions by cross products.
+// No LDS is used; about 140 registers per lane leave room for three waves per SIMD.
+
+#include "mdn_internal.h"
+
+#include <string.h>
+
+#include <type_traits>
+#include <utility>
+
+namespace mdn {
+
+namespace {
+
+constexpr int kLanesOut = 58;
+constexpr int kWaves = 4;
+
+__device__ __forceinline__ uint32_t shl1(uint32_t v) { return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x130, 0xF, 0xF, true); }
+__device__ __forceinline__ uint32_t shr1(uint32_t v) { return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x138, 0xF, 0xF, true); }
+__device__ __forceinline__ float shl1f(float v) { return __uint_as_float(shl1(__float_as_uint(v))); }
+__device__ __forceinline__ float shr1f(float v) { return __uint_as_float(shr1(__float_as_uint(v))); }
+__device__ __forceinline__ double shl1d(double v) {
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    return __longlong_as_double((long long)(((uint64_t)shl1((uint32_t)(u >> 32)) << 32) | shl1((uint32_t)u)));
+}
+__device__ __forceinline__ double shr1d(double v) {
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    return __longlong_as_double((long long)(((uint64_t)shr1((uint32_t)(u >> 32)) << 32) | shr1((uint32_t)u)));
+}
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+#define MDN_GLOBAL __attribute__((address_space(1)))
+template <typename T> __device__ __forceinline__ float ldo(const T* base, uint32_t elem) {
+    const MDN_GLOBAL char* b = (const MDN_GLOBAL char*)(base);
+    return (float)*(const MDN_GLOBAL T*)(b + elem * (uint32_t)sizeof(T));
+}
+
+struct SelImage {
+    const void* z;
+    uint8_t* s;
+    int64_t z_row, z_plane, s_pitch;
+    int32_t W, H, C;
+    int32_t nsx, strip_begin, rows;     // strips across, first strip, rows per strip
+};
+
+struct SelWalkArgs {
+    SelImage single;
+    const SelImage* imgs;
+    int32_t n_imgs, n_strips;
+    int32_t q_theta, q_s, q_c, half;
+    double s_lim[kMaxThr];      // 100 t^2: box sums of squared differences are 100 x the box mean
+    double c_k2[kMaxThr];       // (2t/(1+t^2))^2, or -1 when t <= 0 (always reached)
+    double bcos[kMaxTheta / 2], bsin[kMaxTheta / 2];
+};
+
+struct P3 {
+    double A, B, C;
+};
+
+template <int I>
+using IC = std::integral_constant<int, I>;
+template <typename F, int... Is>
+__device__ __forceinline__ void unroll(F&& f, std::integer_sequence<int, Is...>) {
+    (f(IC<Is>{}), ...);
+}
+
+__device__ __forceinline__ int bucket(double a, double b, double c, const SelWalkArgs& sp) {
+    const double tr = a + c;
+    const double dd = a - c;
+    const double m2 = dd * dd + 4.0 * b * b;
+    int qs = 0;
+    for (int j = 0; j < sp.q_s - 1; ++j) {
+        const double d = 2.0 * sp.s_lim[j] - tr;
+        qs += (d <= 0.0 || m2 >= d * d) ? 1 : 0;
+    }
+    int qc = 0;
+    const double tr2 = tr * tr;
+    for (int j = 0; j < sp.q_c - 1; ++j) {
+        const double k2 = sp.c_k2[j];
+        qc += (k2 < 0.0 || (tr > 0.0 && m2 >= k2 * tr2)) ? 1 : 0;
+    }
+    const double X = c - a, Y = -2.0 * b;
+    int qt;
+    if (X == 0.0 && Y == 0.0) {
+        qt = sp.half;
+    } else {
+        const bool upper = (Y > 0.0) || (Y == 0.0 && X > 0.0);
+        const double px = upper ? X : -X, py = upper ? Y : -Y;
+        int k = 0;
+        for (int j = 0; j < sp.half - 1; ++j) k += (sp.bcos[j] * py - sp.bsin[j] * px >= 0.0) ? 1 : 0;
+        qt = k + (upper ? 0 : sp.half);
+    }
+    return (qt * sp.q_s + qs) * sp.q_c + qc;
+}
+
+template <typename TZ, int C>
+__global__ __launch_bounds__(64 * kWaves) void k_select_walk(SelWalkArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    for (int strip = blockIdx.x * kWaves + wave; strip < a.n_strips; strip += gridDim.x * kWaves) {
+        SelImage im;
+        if (a.imgs == nullptr) {
+            im = a.single;
+        } else {
+            int lo = 0, hi = a.n_imgs - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (a.imgs[mid].strip_begin <= strip) lo = mid; else hi = mid - 1;
+            }
+            im = a.imgs[lo];
+        }
+        const int local = strip - im.strip_begin;
+        const int sy = local / im.nsx, sx = local - sy * im.nsx;
+        const int W = im.W, H = im.H;
+        const int xs = sx * kLanesOut, ys = sy * im.rows;
+        const int ye = min(ys + im.rows, H);
+        const int x = xs - 3 + lane;
+        const int xc = clampi(x, 0, W - 1);
+        const bool out_lane = lane >= 3 && lane < 3 + kLanesOut && x < W;
+        const int lane_x0 = 3 - xs, lane_xw = W - 1 - xs + 3;
+        const bool fix_left = lane_x0 >= 0, fix_right = lane_xw <= 63;
+        const TZ* zb = static_cast<const TZ*>(im.z);
+        const uint32_t zrow = (uint32_t)im.z_row, zpl = (uint32_t)im.z_plane;
+
+        auto load = [&](int row, float v[C]) {
+            const uint32_t o = (uint32_t)clampi(row, 0, H - 1) * zrow + (uint32_t)xc;
+#pragma unroll
+            for (int c = 0; c < C; ++c) v[c] = ldo(zb, o + c * zpl);
+        };
+        // horizontally summed products at an in-image row from its rows (above, centre, below)
+        auto hrow = [&](const float zu[C], const float zm[C], const float zd[C]) {
+            P3 p{0.0, 0.0, 0.0};
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const double dx = (double)shl1f(zm[c]) - (double)shr1f(zm[c]);
+                const double dy = (double)zd[c] - (double)zu[c];
+                p.A += dx * dx;
+                p.B += dx * dy;
+                p.C += dy * dy;
+            }
+            if (fix_left) {
+                const double A0 = readlane_d(p.A, lane_x0), B0 = readlane_d(p.B, lane_x0), C0 = readlane_d(p.C, lane_x0);
+                if (x < 0) {
+                    p.A = A0;
+                    p.B = B0;
+                    p.C = C0;
+                }
+            }
+            if (fix_right) {
+                const double A1 = readlane_d(p.A, lane_xw), B1 = readlane_d(p.B, lane_xw), C1 = readlane_d(p.C, lane_xw);
+                if (x > W - 1) {
+                    p.A = A1;
+                    p.B = B1;
+                    p.C = C1;
+                }
+            }
+            const double A1 = shl1d(p.A), A2 = shl1d(A1), Am1 = shr1d(p.A), Am2 = shr1d(Am1);
+            const double B1 = shl1d(p.B), B2 = shl1d(B1), Bm1 = shr1d(p.B), Bm2 = shr1d(Bm1);
+            const double C1 = shl1d(p.C), C2 = shl1d(C1), Cm1 = shr1d(p.C), Cm2 = shr1d(Cm1);
+            return P3{((Am2 + Am1) + p.A) + (A1 + A2), ((Bm2 + Bm1) + p.B) + (B1 + B2), ((Cm2 + Cm1) + p.C) + (C1 + C2)};
+        };
+        auto hrow_at = [&](int r) {      // row cl(r), loading its three input rows
+            const int c = clampi(r, 0, H - 1);
+            float zu[C], zm[C], zd[C];
+            load(c - 1, zu);
+            load(c, zm);
+            load(c + 1, zd);
+            return hrow(zu, zm, zd);
+        };
+
+        // ring: h(r) in hr[(r - ys) mod 5]; rows ys-2 .. ys+1 first
+        P3 hr[5];
+        float z1[C], z2[C];
+        hr[3] = hrow_at(ys - 2);
+        hr[4] = hrow_at(ys - 1);
+        hr[0] = hrow_at(ys);
+        hr[1] = hrow_at(ys + 1);
+        load(ys + 1, z1);
+        load(ys + 2, z2);
+        for (int y0 = ys; y0 < ye; y0 += 10) {
+            unroll([&](auto ic) {
+                constexpr int I = decltype(ic)::value;
+                const int y = y0 + I;
+                float z3[C];
+                load(y + 3, z3);
+                // h(y+2): rows y+1, y+2, y+3; below the last image row it repeats h(H-1)
+                constexpr int slot = (I + 2) % 5;
+                constexpr int prev = (I + 1) % 5;
+                hr[slot] = (y + 2 <= H - 1) ? hrow(z1, z2, z3) : hr[prev];
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    z1[c] = z2[c];
+                    z2[c] = z3[c];
+                }
+                const double sa = (((hr[0].A + hr[1].A) + hr[2].A) + hr[3].A) + hr[4].A;
+                const double sb = (((hr[0].B + hr[1].B) + hr[2].B) + hr[3].B) + hr[4].B;
+                const double sc = (((hr[0].C + hr[1].C) + hr[2].C) + hr[3].C) + hr[4].C;
+                const int s = bucket(sa, sb, sc, a);
+                if (out_lane && y < ye) *((MDN_GLOBAL uint8_t*)im.s + (uint32_t)y * (uint32_t)im.s_pitch + (uint32_t)x) = (uint8_t)s;
+            }, std::make_integer_sequence<int, 10>{});
+        }
+    }
+}
+
+}  // namespace
+
+int select_walk_rows(int w, int h, int ncu) {
+    // enough strips to give every SIMD a few waves, at most 60 rows (a multiple of 10)
+    const int nsx = (w + kLanesOut - 1) / kLanesOut;
+    int rows = 60;
+    while (rows > 10 && (int64_t)nsx * ((h + rows - 1) / rows) < (int64_t)ncu * 4 * 3) rows -= 10;
+    return rows;
+}
+
+void fill_sel_consts(const mdn_level& lvl, SelWalkArgs& a) {
+    a.q_theta = lvl.q_theta;
+    a.q_s = lvl.q_s;
+    a.q_c = lvl.q_c;
+    a.half = lvl.q_theta / 2;
+    for (int j = 0; j < lvl.q_s - 1; ++j) {
+        const double t = lvl.t_s[j] > 0.0 ? lvl.t_s[j] : 0.0;
+        a.s_lim[j] = 100.0 * t * t;
+    }
+    for (int j = 0; j < lvl.q_c - 1; ++j) {
+        const double t = lvl.t_c[j];
+        if (t <= 0.0) {
+            a.c_k2[j] = -1.0;
+        } else {
+            const double k = 2.0 * t / (1.0 + t * t);
+            a.c_k2[j] = k * k;
+        }
+    }
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int k = 1; k < lvl.q_theta / 2; ++k) {
+        const double ang = two_pi * (double)k / (double)lvl.q_theta;
+        a.bcos[k - 1] = cos(ang);
+        a.bsin[k - 1] = sin(ang);
+    }
+}
+
+mdn_status launch_select_walk(const mdn_image& z, const mdn_level& lvl, uint8_t* s, int64_t s_pitch, hipStream_t st) {
+    if (z.width == 0 || z.height == 0) return MDN_OK;
+    int dev = 0, ncu = 256;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    SelWalkArgs a;
+    memset(&a, 0, sizeof(a));
+    SelImage& im = a.single;
+    im.z = z.data;
+    im.s = s;
+    im.z_row = z.row_pitch;
+    im.z_plane = z.plane_pitch;
+    im.s_pitch = s_pitch;
+    im.W = z.width;
+    im.H = z.height;
+    im.C = z.channels;
+    im.nsx = (z.width + kLanesOut - 1) / kLanesOut;
+    im.rows = select_walk_rows(z.width, z.height, ncu);
+    im.strip_begin = 0;
+    a.imgs = nullptr;
+    a.n_imgs = 1;
+    a.n_strips = im.nsx * ((z.height + im.rows - 1) / im.rows);
+    fill_sel_consts(lvl, a);
+    const int blocks = (a.n_strips + kWaves - 1) / kWaves;
+    const int grid = blocks < 8 * ncu ? blocks : 8 * ncu;
+    if (z.channels == 3) {
+        if (z.dtype == MDN_F16) k_select_walk<_Float16, 3><<<grid, 64 * kWaves, 0, st>>>(a);
+        else k_select_walk<float, 3><<<grid, 64 * kWaves, 0, st>>>(a);
+    } else {
+        if (z.dtype == MDN_F16) k_select_walk<_Float16, 1><<<grid, 64 * kWaves, 0, st>>>(a);
+        else k_select_walk<float, 1><<<grid, 64 * kWaves, 0, st>>>(a);
+    }
+    return check_launch("select_walk");
+}
+
+}  // namespace mdn

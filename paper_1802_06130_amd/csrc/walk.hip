@@ -2,7 +2,7 @@
 // 7x7 denoise filters on colour images, float16 filter coefficients resident in LDS and float32
 // accumulation. The selector s(i) comes from the float64 selection pass as a uint8 map.
 //
-// Work decomposition. A wavefront owns a strip of 58 output columns and 56 output rows; its 64
+// Work decomposition. A wavefront owns a strip of 58 output columns and 14-56 output rows; its 64
 // lanes hold the columns x0-3 .. x0+60 (a 3-column halo on each side) and walk down the strip one
 // output row per step. Persistent 512-thread workgroups (one per CU, two waves per SIMD; the bank
 // fills 145 KB of the 160 KB LDS) take strips round-robin from a list that may span many images.
@@ -38,21 +38,24 @@ typedef _Float16 h2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u4 __attribute__((ext_vector_type(4)));
 
 constexpr int kLanesOut = 58;          // output columns per wave
-constexpr int kStripRows = 56;         // output rows per strip (multiple of 14, even)
 constexpr int kWaves = MDN_WALK_WAVES;  // waves per workgroup
 constexpr int kRows = 14;              // coefficient rows per (bucket, channel): 7 f + 7 g
 constexpr int kRowBytes = 16;          // 8 halves per row (7 taps + 0)
 constexpr int kBucketBytes = 3 * kRows * kRowBytes;   // 672
 constexpr int kMaxK = 160 * 1024 / kBucketBytes;      // 243 buckets fit in LDS
 
-__device__ __forceinline__ uint32_t shl1(uint32_t v) { return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130, 0xF, 0xF, false); }
-__device__ __forceinline__ uint32_t shr1(uint32_t v) { return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138, 0xF, 0xF, false); }
+// lane i <- lane i+1 (shl) / lane i-1 (shr); the lane without a source reads 0 (bound_ctrl)
+__device__ __forceinline__ uint32_t shl1(uint32_t v) { return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x130, 0xF, 0xF, true); }
+__device__ __forceinline__ uint32_t shr1(uint32_t v) { return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x138, 0xF, 0xF, true); }
 __device__ __forceinline__ float shl1f(float v) { return __uint_as_float(shl1(__float_as_uint(v))); }
 __device__ __forceinline__ float shr1f(float v) { return __uint_as_float(shr1(__float_as_uint(v))); }
 __device__ __forceinline__ uint32_t pack2(float lo, float hi) {
-    const _Float16 a = (_Float16)lo, b = (_Float16)hi;
-    return (uint32_t)__builtin_bit_cast(unsigned short, a) | ((uint32_t)__builtin_bit_cast(unsigned short, b) << 16);
+    const h2 v = {(_Float16)lo, (_Float16)hi};
+    return __builtin_bit_cast(uint32_t, v);
 }
+// (lo half of a, lo half of b), (hi of a, hi of b)
+__device__ __forceinline__ uint32_t lolo(uint32_t a, uint32_t b) { return __builtin_amdgcn_perm(b, a, 0x05040100u); }
+__device__ __forceinline__ uint32_t hihi(uint32_t a, uint32_t b) { return __builtin_amdgcn_perm(b, a, 0x07060302u); }
 __device__ __forceinline__ float dot2(uint32_t c, uint32_t w, float acc) {
     return __builtin_amdgcn_fdot2(__builtin_bit_cast(h2, c), __builtin_bit_cast(h2, w), acc, false);
 }
@@ -67,7 +70,7 @@ struct WalkImage {
     int32_t z_dtype, uc_dtype, uc_rgb, o_dtype, o_rgb;
     int32_t nsx;            // strips across
     int32_t strip_begin;    // first strip index of this image in the list
-    int32_t pad;
+    int32_t rows;           // output rows per strip (a multiple of 14)
     const uint8_t* s_map;   // selector of this level (from the selection pass)
     int64_t s_pitch;
 };
@@ -98,11 +101,18 @@ __device__ __forceinline__ void unroll(F&& f, std::integer_sequence<int, Is...>)
     (f(IC<Is>{}), ...);
 }
 
-template <typename T> __device__ __forceinline__ float ldt(const void* p, int64_t off) {
-    return (float)static_cast<const T*>(p)[off];
+// element access through a wave-uniform global base and a 32-bit byte offset (saddr + voffset)
+#define MDN_GLOBAL __attribute__((address_space(1)))
+template <typename T> __device__ __forceinline__ float ldo(const T* base, uint32_t elem) {
+    const MDN_GLOBAL char* b = (const MDN_GLOBAL char*)(base);
+    return (float)*(const MDN_GLOBAL T*)(b + elem * (uint32_t)sizeof(T));
 }
-template <typename T> __device__ __forceinline__ void stt(void* p, int64_t off, float v) {
-    static_cast<T*>(p)[off] = (T)v;
+template <typename T> __device__ __forceinline__ void sto(T* base, uint32_t elem, float v) {
+    MDN_GLOBAL char* b = (MDN_GLOBAL char*)(base);
+    *(MDN_GLOBAL T*)(b + elem * (uint32_t)sizeof(T)) = (T)v;
+}
+__device__ __forceinline__ int ldo_u8(const uint8_t* base, uint32_t elem) {
+    return *((const MDN_GLOBAL uint8_t*)base + elem);
 }
 
 // Filtering pass of the column walk (the selector map comes from the selection pass).
@@ -110,7 +120,8 @@ template <typename T> __device__ __forceinline__ void stt(void* p, int64_t off, 
 template <typename TZ, typename TU, typename TO>
 __global__ __launch_bounds__(64 * MDN_WALK_WAVES) void k_walk(WalkArgs a) {
     extern __shared__ __attribute__((aligned(16))) unsigned char bank[];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);     // wave-uniform
 
     // ---- bank into LDS: row (k, c, r) = 7 taps + 0, float16
     {
@@ -148,7 +159,7 @@ __global__ __launch_bounds__(64 * MDN_WALK_WAVES) void k_walk(WalkArgs a) {
         const int local = strip - im.strip_begin;
         const int sy = local / im.nsx, sx = local - sy * im.nsx;
         const int W = im.W, H = im.H;
-        const int xs = sx * kLanesOut, ys = sy * kStripRows;
+        const int xs = sx * kLanesOut, ys = sy * im.rows;
         const int x = xs - 3 + lane;
         const int xc = clampi(x, 0, W - 1);
         const bool out_lane = lane >= 3 && lane < 3 + kLanesOut && x < W;
@@ -165,36 +176,40 @@ __global__ __launch_bounds__(64 * MDN_WALK_WAVES) void k_walk(WalkArgs a) {
 
         auto load_rgb = [&](int row, float v[3]) {
             const uint32_t o = (uint32_t)clampi(row, 0, H - 1) * zrow + (uint32_t)xc;
-            v[0] = (float)zb[o];
-            v[1] = (float)zb[o + zpl];
-            v[2] = (float)zb[o + 2 * zpl];
+            v[0] = ldo(zb, o);
+            v[1] = ldo(zb, o + zpl);
+            v[2] = ldo(zb, o + 2 * zpl);
         };
         // a window row: w[c][0..2] = pairs (x-3,x-2) (x-1,x) (x+1,x+2) of channel c,
-        // w[0][3] = (Y(x+3), Cb(x+3)) and w[2][3] = (Cr(x+3), 0) shared by the three channels
+        // w[0][3] = (Y(x+3), Cb(x+3)) and w[2][3] = (Cr(x+3), 0) shared by the three channels.
+        // Y and Cb travel packed in one register, Cr in another, through the DPP shifts.
         auto fine_row = [&](const float rgb[3], uint32_t w[3][4]) {
             float yv, cb, cr;
             Ycc::from_rgb(rgb[0], rgb[1], rgb[2], yv, cb, cr);
-            const float v[3] = {yv, cb, cr};
-            float p3[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const float p1 = shl1f(v[c]), p2 = shl1f(p1);
-                p3[c] = shl1f(p2);
-                const float m1 = shr1f(v[c]), m2 = shr1f(m1), m3 = shr1f(m2);
-                w[c][0] = pack2(m3, m2);
-                w[c][1] = pack2(m1, v[c]);
-                w[c][2] = pack2(p1, p2);
-            }
-            w[0][3] = pack2(p3[0], p3[1]);
-            w[2][3] = pack2(p3[2], 0.0f);
+            const uint32_t a0 = pack2(yv, cb), b0 = pack2(cr, 0.0f);
+            const uint32_t a1 = shl1(a0), a2 = shl1(a1), a3 = shl1(a2);
+            const uint32_t am1 = shr1(a0), am2 = shr1(am1), am3 = shr1(am2);
+            const uint32_t b1 = shl1(b0), b2 = shl1(b1), b3 = shl1(b2);
+            const uint32_t bm1 = shr1(b0), bm2 = shr1(bm1), bm3 = shr1(bm2);
+            w[0][0] = lolo(am3, am2);
+            w[0][1] = lolo(am1, a0);
+            w[0][2] = lolo(a1, a2);
+            w[1][0] = hihi(am3, am2);
+            w[1][1] = hihi(am1, a0);
+            w[1][2] = hihi(a1, a2);
+            w[2][0] = lolo(bm3, bm2);
+            w[2][1] = lolo(bm1, b0);
+            w[2][2] = lolo(b1, b2);
+            w[0][3] = a3;
+            w[2][3] = b3;
         };
         auto load_coarse = [&](int cr, float u[3][3]) {
             const uint32_t r0 = (uint32_t)clampi(cr, 0, im.Hc - 1) * urow;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                u[0][c] = (float)ub[r0 + c * upl + uc0];
-                u[1][c] = (float)ub[r0 + c * upl + uc1];
-                u[2][c] = (float)ub[r0 + c * upl + uc2];
+                u[0][c] = ldo(ub, r0 + c * upl + uc0);
+                u[1][c] = ldo(ub, r0 + c * upl + uc1);
+                u[2][c] = ldo(ub, r0 + c * upl + uc2);
             }
         };
         auto coarse_row = [&](float u[3][3], uint32_t w[3][4]) {
@@ -202,18 +217,26 @@ __global__ __launch_bounds__(64 * MDN_WALK_WAVES) void k_walk(WalkArgs a) {
 #pragma unroll
                 for (int j = 0; j < 3; ++j) Ycc::from_rgb(u[j][0], u[j][1], u[j][2], u[j][0], u[j][1], u[j][2]);
             }
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const float dm2 = shl1f(shl1f(u[0][c]));      // floor(x/2) - 2 (from lane x+2)
-                const float dp1 = shl1f(shl1f(u[1][c]));      // floor(x/2) + 1
-                const float dm1 = shr1f(shr1f(u[1][c]));      // floor(x/2) - 1 (from lane x-2)
-                const float dp2 = shr1f(shr1f(u[2][c]));      // floor(x/2) + 2
-                w[c][0] = pack2(u[0][c], dm2);
-                w[c][1] = pack2(dm1, u[1][c]);
-                w[c][2] = pack2(dp1, dp2);
-            }
-            w[0][3] = pack2(u[2][0], u[2][1]);
-            w[2][3] = pack2(u[2][2], 0.0f);
+            // u[0], u[1], u[2]: columns floor(x/2) - 3, floor(x/2), floor(x/2) + 3
+            const uint32_t a0 = pack2(u[0][0], u[0][1]), b0 = pack2(u[0][2], 0.0f);
+            const uint32_t a1 = pack2(u[1][0], u[1][1]), b1 = pack2(u[1][2], 0.0f);
+            const uint32_t a2 = pack2(u[2][0], u[2][1]), b2 = pack2(u[2][2], 0.0f);
+            // lane x+2 holds floor(x/2)+1, lane x-2 floor(x/2)-1
+            const uint32_t am2 = shl1(shl1(a0)), bm2 = shl1(shl1(b0));     // floor(x/2) - 2
+            const uint32_t ap1 = shl1(shl1(a1)), bp1 = shl1(shl1(b1));     // floor(x/2) + 1
+            const uint32_t am1 = shr1(shr1(a1)), bm1 = shr1(shr1(b1));     // floor(x/2) - 1
+            const uint32_t ap2 = shr1(shr1(a2)), bp2 = shr1(shr1(b2));     // floor(x/2) + 2
+            w[0][0] = lolo(a0, am2);
+            w[0][1] = lolo(am1, a1);
+            w[0][2] = lolo(ap1, ap2);
+            w[1][0] = hihi(a0, am2);
+            w[1][1] = hihi(am1, a1);
+            w[1][2] = hihi(ap1, ap2);
+            w[2][0] = lolo(b0, bm2);
+            w[2][1] = lolo(bm1, b1);
+            w[2][2] = lolo(bp1, bp2);
+            w[0][3] = a2;
+            w[2][3] = b2;
         };
 
         // ring slots: fine row r sits in fw[r mod 7], coarse row cr in cw[cr mod 7] (ys = 0 mod 14)
@@ -236,9 +259,9 @@ __global__ __launch_bounds__(64 * MDN_WALK_WAVES) void k_walk(WalkArgs a) {
                 coarse_row(u, cw[(d + 7) % 7]);
             }
             load_rgb(ys + 3, znext);
-            snext = sb[(uint32_t)clampi(ys, 0, H - 1) * spitch + (uint32_t)xc];
+            snext = ldo_u8(sb, (uint32_t)clampi(ys, 0, H - 1) * spitch + (uint32_t)xc);
         }
-        for (int y0 = ys; y0 < ys + kStripRows; y0 += 14) {
+        for (int y0 = ys; y0 < ys + im.rows && y0 < H; y0 += 14) {
             unroll([&](auto ic) {
                 constexpr int I = decltype(ic)::value;
                 const int y = y0 + I;
@@ -246,7 +269,7 @@ __global__ __launch_bounds__(64 * MDN_WALK_WAVES) void k_walk(WalkArgs a) {
                 fine_row(znext, fw[(I + 3) % 7]);
                 const int s = snext;
                 load_rgb(y + 4, znext);
-                snext = sb[(uint32_t)clampi(y + 1, 0, H - 1) * spitch + (uint32_t)xc];
+                snext = ldo_u8(sb, (uint32_t)clampi(y + 1, 0, H - 1) * spitch + (uint32_t)xc);
                 float unext[3][3];
                 if constexpr (I & 1) load_coarse(((y + 1) >> 1) + 3, unext);
                 const uint8_t* bp = bank + (size_t)s * kBucketBytes;
@@ -278,7 +301,7 @@ __global__ __launch_bounds__(64 * MDN_WALK_WAVES) void k_walk(WalkArgs a) {
                     if (im.o_rgb) Ycc::to_rgb(acc[0], acc[1], acc[2], acc[0], acc[1], acc[2]);
                     const uint32_t off = (uint32_t)y * (uint32_t)im.o_row + (uint32_t)x;
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) stt<TO>(im.out, off + c * (uint32_t)im.o_plane, acc[c]);
+                    for (int c = 0; c < 3; ++c) sto(static_cast<TO*>(im.out), off + c * (uint32_t)im.o_plane, acc[c]);
                 }
                 // after an odd row the next row has a new floor(y/2): the coarse row floor/2 + 3 enters
                 if constexpr (I & 1) coarse_row(unext, cw[((I + 1) / 2 + 3) % 7]);
@@ -319,8 +342,16 @@ static void fill_walk_image(WalkImage& wi, const mdn_image& z, const mdn_image& 
     wi.strip_begin = begin;
 }
 
-int walk_strips(int w, int h) {
-    return ((w + kLanesOut - 1) / kLanesOut) * ((h + kStripRows - 1) / kStripRows);
+// rows per strip: 56 when the image gives every wave slot a few strips, else down to 14
+int walk_rows(int w, int h, int wave_slots) {
+    const int nsx = (w + kLanesOut - 1) / kLanesOut;
+    int rows = 56;
+    while (rows > 14 && (int64_t)nsx * ((h + rows - 1) / rows) < (int64_t)wave_slots * 3) rows -= 14;
+    return rows;
+}
+
+int walk_strips(int w, int h, int rows) {
+    return ((w + kLanesOut - 1) / kLanesOut) * ((h + rows - 1) / rows);
 }
 
 template <typename TZ, typename TU, typename TO>
@@ -348,19 +379,20 @@ mdn_status launch_walk(const mdn_image& z, const mdn_image& uc, const mdn_level&
     }
     WalkArgs a;
     memset(&a, 0, sizeof(a));
+    int dev = 0, ncu = 256;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     fill_walk_image(a.single, z, uc, out, 0);
     a.single.s_map = smap;
     a.single.s_pitch = s_pitch;
+    a.single.rows = walk_rows(z.width, z.height, ncu * kWaves);
     a.imgs = nullptr;
     a.n_imgs = 1;
-    a.n_strips = walk_strips(z.width, z.height);
+    a.n_strips = walk_strips(z.width, z.height, a.single.rows);
     a.coeffs = lvl.coeffs;
     a.coeff_dtype = lvl.coeff_dtype;
     a.K = lvl.q_theta * lvl.q_s * lvl.q_c;
     const size_t lds = walk_lds_bytes(a.K);
-    int dev = 0, ncu = 256;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     const int blocks = (a.n_strips + kWaves - 1) / kWaves;
     const int grid = blocks < ncu ? blocks : ncu;
     const bool zh = z.dtype == MDN_F16, uh = uc.dtype == MDN_F16, oh = out.dtype == MDN_F16;
