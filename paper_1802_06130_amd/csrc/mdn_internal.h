@@ -80,7 +80,11 @@ struct SelectArg {
 void fill_select_arg(const mdn_level& lvl, SelectArg& a);
 
 // Launchers (stream work only; arguments already validated).
-mdn_status launch_down2(const mdn_image& in, const mdn_image& out, hipStream_t st);
+mdn_status launch_down2_tiled(const mdn_image& in, const mdn_image& out, hipStream_t st);
+mdn_status launch_down2_walk(const mdn_image& in, const mdn_image& out, hipStream_t st);
+inline mdn_status launch_down2(const mdn_image& in, const mdn_image& out, hipStream_t st) {
+    return launch_down2_walk(in, out, st);
+}
 mdn_status launch_select_apply(const mdn_image& z, const mdn_image* uc, const uint8_t* s_in,
                                int64_t s_pitch, uint8_t* s_out, const mdn_level& lvl,
                                const mdn_image* out, hipStream_t st);

@@ -78,7 +78,7 @@ mdn_status launch_typed(const mdn_image& in, const mdn_image& out, hipStream_t s
 
 }  // namespace
 
-mdn_status launch_down2(const mdn_image& in, const mdn_image& out, hipStream_t st) {
+mdn_status launch_down2_tiled(const mdn_image& in, const mdn_image& out, hipStream_t st) {
     if (out.width == 0 || out.height == 0) return MDN_OK;
     if (in.dtype == MDN_F32 && out.dtype == MDN_F32) return launch_typed<float, float>(in, out, st);
     if (in.dtype == MDN_F32 && out.dtype == MDN_F16) return launch_typed<float, __half>(in, out, st);
