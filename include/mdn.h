@@ -210,6 +210,31 @@ mdn_status mdn_quantiles_workspace_size(int64_t n, size_t* bytes);
 mdn_status mdn_quantiles(const double* values, int64_t n, int32_t q, double* out_host, void* ws,
                          size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------------------------------
+ * Batched form: many RGB images of any sizes, level by level, one persistent launch per kernel
+ * and level over all images (pyramid, selection, filtering), optionally as a replayed hipGraph.
+ * --------------------------------------------------------------------------------------- */
+typedef struct mdn_plan mdn_plan;
+
+/* Create a plan for a float16 7x7/7x7 colour bank (K <= 243 per level). The plan copies the
+ * level descriptors and thresholds (the coefficient buffers must stay valid while it is used),
+ * creates its own stream, and allocates its device workspace and tables on first use: creation
+ * and the first batch of a new size are the only calls that allocate. storage: pyramid dtype. */
+mdn_status mdn_plan_create(const mdn_bank* bank, int32_t storage, int32_t max_images, mdn_plan** plan);
+mdn_status mdn_plan_destroy(mdn_plan* plan);
+
+/* Time candidate strip heights of every kernel and level on this batch and keep the fastest
+ * (rows_out, optional host int32[3*levels]: pyramid, selection, filtering rows per level). Runs
+ * the batch once; ordered after prior work on `stream` and before later work. */
+mdn_status mdn_plan_autotune(mdn_plan* plan, const mdn_image* in, const mdn_image* out, int32_t n,
+                             int32_t* rows_out, void* stream);
+
+/* Denoise n images (in[i] -> out[i], RGB, equal sizes per pair, one dtype per side). With
+ * use_graph != 0 the launches are captured once per batch (same images, sizes and buffers) and
+ * replayed afterwards. Ordered after prior work on `stream` and before later work. */
+mdn_status mdn_denoise_batch(mdn_plan* plan, const mdn_image* in, const mdn_image* out, int32_t n,
+                             int32_t use_graph, void* stream);
+
 /* Thread-local description of the last non-OK status (empty string if none). */
 const char* mdn_last_error(void);
 

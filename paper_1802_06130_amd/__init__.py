@@ -7,5 +7,5 @@ from ._lib import (  # noqa: F401
     apply_level, denoise, denoise_workspace_size, header_functions, image, lib,
     pyramid_build, select_filters,
     GRAM_BF16X3, GRAM_F32, X_CROSS_CHANNEL, X_PER_CHANNEL, Gram, level_features, level_thresholds,
-    quantiles, train_accumulate, train_multiscale, train_single, train_solve,
+    quantiles, train_accumulate, train_multiscale, train_single, train_solve, Plan,
 )

@@ -422,3 +422,63 @@ def train_multiscale(pairs, n_trained_levels: int, q_theta: int, q_s: int, q_c: 
                             out_dtype=pz[i][lev].dtype) for i in range(len(pairs))]
         coarse_color = GRAY if C == 1 else YCC
     return Bank(levels), grams, fbs
+
+
+# ----------------------------------------------------------------------------- batched form
+
+def _plan_sigs(L):
+    vp, i32 = ct.c_void_p, ct.c_int32
+    P = ct.POINTER
+    sig = {
+        "mdn_plan_create": [P(MdnBank), i32, i32, P(vp)],
+        "mdn_plan_destroy": [vp],
+        "mdn_plan_autotune": [vp, P(MdnImage), P(MdnImage), i32, P(i32), vp],
+        "mdn_denoise_batch": [vp, P(MdnImage), P(MdnImage), i32, i32, vp],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = ct.c_int
+
+
+class Plan:
+    """Batched denoiser: one persistent launch per kernel and level over a list of images."""
+
+    def __init__(self, bank: Bank, storage: int = F16, max_images: int = 256):
+        _plan_sigs(lib())
+        self.bank = bank                       # keeps the coefficient tensors alive
+        self.levels = len(bank.levels)
+        h = ct.c_void_p()
+        _check(lib().mdn_plan_create(ct.byref(bank.desc()), storage, max_images, ct.byref(h)))
+        self.handle = h
+
+    def _descs(self, ins, outs):
+        n = len(ins)
+        a = (MdnImage * n)(*[image(t, RGB) for t in ins])
+        b = (MdnImage * n)(*[image(t, RGB) for t in outs])
+        return n, a, b
+
+    def autotune(self, ins, outs=None):
+        outs = outs if outs is not None else [_torch().empty_like(t) for t in ins]
+        n, a, b = self._descs(ins, outs)
+        rows = (ct.c_int32 * (3 * self.levels))()
+        _check(lib().mdn_plan_autotune(self.handle, a, b, n, rows, _stream_ptr()))
+        return [tuple(rows[3 * l:3 * l + 3]) for l in range(self.levels)]
+
+    def denoise_batch(self, ins, outs=None, use_graph: bool = True):
+        outs = outs if outs is not None else [_torch().empty_like(t) for t in ins]
+        n, a, b = self._descs(ins, outs)
+        self._keep = (a, b)
+        _check(lib().mdn_denoise_batch(self.handle, a, b, n, 1 if use_graph else 0, _stream_ptr()))
+        return outs
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().mdn_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

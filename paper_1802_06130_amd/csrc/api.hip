@@ -33,6 +33,8 @@ mdn_status check_launch(const char* what) {
 
 int64_t elem_size(int32_t dtype) { return dtype == MDN_F16 ? 2 : 4; }
 
+void clear_error() { g_err[0] = 0; }
+
 namespace {
 
 bool empty(const mdn_image& im) { return im.width == 0 || im.height == 0; }
@@ -121,6 +123,9 @@ mdn_status check_gram(const mdn_gram* g) {
 }
 
 }  // namespace
+
+mdn_status validate_level(const mdn_level* lv, int channels) { return check_level(lv, channels); }
+
 }  // namespace mdn
 
 using namespace mdn;

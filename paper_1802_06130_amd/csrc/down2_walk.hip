@@ -11,7 +11,7 @@
 // sit in an 8-row register ring (fixed slots, the 4-row step body is expanded at compile time);
 // each output row consumes two new input rows.
 
-#include "mdn_internal.h"
+#include "walk_types.h"
 
 #include <string.h>
 
@@ -22,7 +22,7 @@ namespace mdn {
 
 namespace {
 
-constexpr int kOut = 60;        // output columns per wave
+constexpr int kOut = kD2LanesOut;
 constexpr int kWaves = 4;
 
 __device__ __forceinline__ uint32_t shl1(uint32_t v) { return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x130, 0xF, 0xF, true); }
@@ -54,21 +54,6 @@ template <typename F, int... Is>
 __device__ __forceinline__ void unroll(F&& f, std::integer_sequence<int, Is...>) {
     (f(IC<Is>{}), ...);
 }
-
-struct D2Image {
-    const void* in;
-    void* out;
-    int64_t i_row, i_plane, o_row, o_plane;
-    int32_t Wi, Hi, Wo, Ho;
-    int32_t nsx, strip_begin, rows;
-    int32_t pad;
-};
-
-struct D2Args {
-    D2Image single;
-    const D2Image* imgs;
-    int32_t n_imgs, n_strips;
-};
 
 template <typename TI, typename TO, int C>
 __global__ __launch_bounds__(64 * kWaves) void k_down2_walk(D2Args a) {
@@ -147,11 +132,27 @@ int down2_rows(int wo, int ho, int ncu) {
     return rows;
 }
 
+mdn_status launch_down2_args(const D2Args& a, int C, int in_dtype, int out_dtype, hipStream_t st) {
+    if (a.n_strips <= 0) return MDN_OK;
+    const int ncu = device_cus();
+    const int blocks = (a.n_strips + kWaves - 1) / kWaves;
+    const int grid = blocks < 8 * ncu ? blocks : 8 * ncu;
+#define MDN_D2(TI_, TO_, DI_, DO_)                                                        \
+    if (in_dtype == DI_ && out_dtype == DO_) {                                            \
+        if (C == 3) k_down2_walk<TI_, TO_, 3><<<grid, 64 * kWaves, 0, st>>>(a);           \
+        else k_down2_walk<TI_, TO_, 1><<<grid, 64 * kWaves, 0, st>>>(a);                  \
+        return check_launch("down2_walk");                                                \
+    }
+    MDN_D2(float, float, MDN_F32, MDN_F32)
+    MDN_D2(float, _Float16, MDN_F32, MDN_F16)
+    MDN_D2(_Float16, _Float16, MDN_F16, MDN_F16)
+    MDN_D2(_Float16, float, MDN_F16, MDN_F32)
+#undef MDN_D2
+    return fail(MDN_EINVAL, "down2: unsupported dtype pair");
+}
+
 mdn_status launch_down2_walk(const mdn_image& in, const mdn_image& out, hipStream_t st) {
     if (out.width == 0 || out.height == 0) return MDN_OK;
-    int dev = 0, ncu = 256;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     D2Args a;
     memset(&a, 0, sizeof(a));
     D2Image& im = a.single;
@@ -166,24 +167,10 @@ mdn_status launch_down2_walk(const mdn_image& in, const mdn_image& out, hipStrea
     im.Wo = out.width;
     im.Ho = out.height;
     im.nsx = (out.width + kOut - 1) / kOut;
-    im.rows = down2_rows(out.width, out.height, ncu);
+    im.rows = down2_rows(out.width, out.height, device_cus());
     a.n_imgs = 1;
     a.n_strips = im.nsx * ((out.height + im.rows - 1) / im.rows);
-    const int blocks = (a.n_strips + kWaves - 1) / kWaves;
-    const int grid = blocks < 8 * ncu ? blocks : 8 * ncu;
-    const int C = in.channels;
-#define MDN_D2(TI_, TO_, DI_, DO_)                                                        \
-    if (in.dtype == DI_ && out.dtype == DO_) {                                            \
-        if (C == 3) k_down2_walk<TI_, TO_, 3><<<grid, 64 * kWaves, 0, st>>>(a);           \
-        else k_down2_walk<TI_, TO_, 1><<<grid, 64 * kWaves, 0, st>>>(a);                  \
-        return check_launch("down2_walk");                                                \
-    }
-    MDN_D2(float, float, MDN_F32, MDN_F32)
-    MDN_D2(float, _Float16, MDN_F32, MDN_F16)
-    MDN_D2(_Float16, _Float16, MDN_F16, MDN_F16)
-    MDN_D2(_Float16, float, MDN_F16, MDN_F32)
-#undef MDN_D2
-    return fail(MDN_EINVAL, "down2: unsupported dtype pair");
+    return launch_down2_args(a, in.channels, in.dtype, out.dtype, st);
 }
 
 }  // namespace mdn

@@ -11,6 +11,8 @@ namespace mdn {
 
 // ------------------------------------------------------------------------ error state
 void set_error(const char* fmt, ...);
+void clear_error();
+mdn_status validate_level(const mdn_level* lv, int channels);
 mdn_status fail(mdn_status st, const char* fmt, ...);
 mdn_status check_launch(const char* what);
 

@@ -15,7 +15,7 @@
 //   boundary directions by cross products.
 // No LDS is used; about 140 registers per lane leave room for three waves per SIMD.
 
-#include "mdn_internal.h"
+#include "walk_types.h"
 
 #include <string.h>
 
@@ -26,7 +26,7 @@ namespace mdn {
 
 namespace {
 
-constexpr int kLanesOut = 58;
+constexpr int kLanesOut = kSelLanesOut;
 constexpr int kWaves = 4;
 
 __device__ __forceinline__ uint32_t shl1(uint32_t v) { return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x130, 0xF, 0xF, true); }
@@ -53,24 +53,6 @@ template <typename T> __device__ __forceinline__ float ldo(const T* base, uint32
     const MDN_GLOBAL char* b = (const MDN_GLOBAL char*)(base);
     return (float)*(const MDN_GLOBAL T*)(b + elem * (uint32_t)sizeof(T));
 }
-
-struct SelImage {
-    const void* z;
-    uint8_t* s;
-    int64_t z_row, z_plane, s_pitch;
-    int32_t W, H, C;
-    int32_t nsx, strip_begin, rows;     // strips across, first strip, rows per strip
-};
-
-struct SelWalkArgs {
-    SelImage single;
-    const SelImage* imgs;
-    int32_t n_imgs, n_strips;
-    int32_t q_theta, q_s, q_c, half;
-    double s_lim[kMaxThr];      // 100 t^2: box sums of squared differences are 100 x the box mean
-    double c_k2[kMaxThr];       // (2t/(1+t^2))^2, or -1 when t <= 0 (always reached)
-    double bcos[kMaxTheta / 2], bsin[kMaxTheta / 2];
-};
 
 struct P3 {
     double A, B, C;
@@ -257,11 +239,23 @@ void fill_sel_consts(const mdn_level& lvl, SelWalkArgs& a) {
     }
 }
 
+mdn_status launch_select_args(const SelWalkArgs& a, int channels, int z_dtype, hipStream_t st) {
+    if (a.n_strips <= 0) return MDN_OK;
+    const int ncu = device_cus();
+    const int blocks = (a.n_strips + kWaves - 1) / kWaves;
+    const int grid = blocks < 8 * ncu ? blocks : 8 * ncu;
+    if (channels == 3) {
+        if (z_dtype == MDN_F16) k_select_walk<_Float16, 3><<<grid, 64 * kWaves, 0, st>>>(a);
+        else k_select_walk<float, 3><<<grid, 64 * kWaves, 0, st>>>(a);
+    } else {
+        if (z_dtype == MDN_F16) k_select_walk<_Float16, 1><<<grid, 64 * kWaves, 0, st>>>(a);
+        else k_select_walk<float, 1><<<grid, 64 * kWaves, 0, st>>>(a);
+    }
+    return check_launch("select_walk");
+}
+
 mdn_status launch_select_walk(const mdn_image& z, const mdn_level& lvl, uint8_t* s, int64_t s_pitch, hipStream_t st) {
     if (z.width == 0 || z.height == 0) return MDN_OK;
-    int dev = 0, ncu = 256;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     SelWalkArgs a;
     memset(&a, 0, sizeof(a));
     SelImage& im = a.single;
@@ -274,22 +268,13 @@ mdn_status launch_select_walk(const mdn_image& z, const mdn_level& lvl, uint8_t*
     im.H = z.height;
     im.C = z.channels;
     im.nsx = (z.width + kLanesOut - 1) / kLanesOut;
-    im.rows = select_walk_rows(z.width, z.height, ncu);
+    im.rows = select_walk_rows(z.width, z.height, device_cus());
     im.strip_begin = 0;
     a.imgs = nullptr;
     a.n_imgs = 1;
     a.n_strips = im.nsx * ((z.height + im.rows - 1) / im.rows);
     fill_sel_consts(lvl, a);
-    const int blocks = (a.n_strips + kWaves - 1) / kWaves;
-    const int grid = blocks < 8 * ncu ? blocks : 8 * ncu;
-    if (z.channels == 3) {
-        if (z.dtype == MDN_F16) k_select_walk<_Float16, 3><<<grid, 64 * kWaves, 0, st>>>(a);
-        else k_select_walk<float, 3><<<grid, 64 * kWaves, 0, st>>>(a);
-    } else {
-        if (z.dtype == MDN_F16) k_select_walk<_Float16, 1><<<grid, 64 * kWaves, 0, st>>>(a);
-        else k_select_walk<float, 1><<<grid, 64 * kWaves, 0, st>>>(a);
-    }
-    return check_launch("select_walk");
+    return launch_select_args(a, z.channels, z.dtype, st);
 }
 
 }  // namespace mdn

@@ -19,7 +19,7 @@
 // Window rows live in fixed register slots (row r in slot r mod 7); the 14-row step body is
 // expanded at compile time, so no register ever moves when the windows slide.
 
-#include "mdn_internal.h"
+#include "walk_types.h"
 
 #include <string.h>
 
@@ -37,7 +37,7 @@ namespace {
 typedef _Float16 h2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u4 __attribute__((ext_vector_type(4)));
 
-constexpr int kLanesOut = 58;          // output columns per wave
+constexpr int kLanesOut = kWalkLanesOut;
 constexpr int kWaves = MDN_WALK_WAVES;  // waves per workgroup
 constexpr int kRows = 14;              // coefficient rows per (bucket, channel): 7 f + 7 g
 constexpr int kRowBytes = 16;          // 8 halves per row (7 taps + 0)
@@ -59,29 +59,6 @@ __device__ __forceinline__ uint32_t hihi(uint32_t a, uint32_t b) { return __buil
 __device__ __forceinline__ float dot2(uint32_t c, uint32_t w, float acc) {
     return __builtin_amdgcn_fdot2(__builtin_bit_cast(h2, c), __builtin_bit_cast(h2, w), acc, false);
 }
-
-// One image of the strip list.
-struct WalkImage {
-    const void* z;          // RGB input of the level
-    const void* uc;         // coarser output (YCbCr, or RGB at the coarsest level)
-    void* out;
-    int64_t z_row, z_plane, uc_row, uc_plane, o_row, o_plane;
-    int32_t W, H, Wc, Hc;
-    int32_t z_dtype, uc_dtype, uc_rgb, o_dtype, o_rgb;
-    int32_t nsx;            // strips across
-    int32_t strip_begin;    // first strip index of this image in the list
-    int32_t rows;           // output rows per strip (a multiple of 14)
-    const uint8_t* s_map;   // selector of this level (from the selection pass)
-    int64_t s_pitch;
-};
-
-struct WalkArgs {
-    WalkImage single;           // used when imgs == nullptr
-    const WalkImage* imgs;      // device array (batch) or null
-    int32_t n_imgs, n_strips;
-    const void* coeffs;         // [K][3][98], float16 or float32
-    int32_t coeff_dtype, K;
-};
 
 __device__ __forceinline__ float ld(const void* p, int dtype, int64_t off) {
     return dtype == MDN_F16 ? (float)static_cast<const _Float16*>(p)[off] : static_cast<const float*>(p)[off];
@@ -267,7 +244,9 @@ __global__ __launch_bounds__(64 * MDN_WALK_WAVES) void k_walk(WalkArgs a) {
                 const int y = y0 + I;
                 // the prefetched row y+3 enters the fine window; prefetch row y+4 and s(y+1)
                 fine_row(znext, fw[(I + 3) % 7]);
-                const int s = snext;
+                // a selector value outside the bank reads bucket 0 and yields NaN (memory-safe)
+                const bool s_ok = snext < a.K;
+                const int s = s_ok ? snext : 0;
                 load_rgb(y + 4, znext);
                 snext = ldo_u8(sb, (uint32_t)clampi(y + 1, 0, H - 1) * spitch + (uint32_t)xc);
                 float unext[3][3];
@@ -298,6 +277,7 @@ __global__ __launch_bounds__(64 * MDN_WALK_WAVES) void k_walk(WalkArgs a) {
                     acc[c] = af + ag;
                 }
                 if (out_lane && y < H) {
+                    if (!s_ok) acc[0] = acc[1] = acc[2] = __builtin_nanf("");
                     if (im.o_rgb) Ycc::to_rgb(acc[0], acc[1], acc[2], acc[0], acc[1], acc[2]);
                     const uint32_t off = (uint32_t)y * (uint32_t)im.o_row + (uint32_t)x;
 #pragma unroll
@@ -318,7 +298,14 @@ bool walk_supported(const mdn_level& lvl, int channels) {
 
 size_t walk_lds_bytes(int K) { return (size_t)K * kBucketBytes; }
 
-static void fill_walk_image(WalkImage& wi, const mdn_image& z, const mdn_image& uc, const mdn_image& out, int begin) {
+int device_cus() {
+    int dev = 0, ncu = 256;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    return ncu;
+}
+
+void fill_walk_image(WalkImage& wi, const mdn_image& z, const mdn_image& uc, const mdn_image& out, int begin) {
     memset(&wi, 0, sizeof(wi));
     wi.z = z.data;
     wi.uc = uc.data;
@@ -350,21 +337,40 @@ int walk_rows(int w, int h, int wave_slots) {
     return rows;
 }
 
-int walk_strips(int w, int h, int rows) {
-    return ((w + kLanesOut - 1) / kLanesOut) * ((h + rows - 1) / rows);
+static int g_walk_init = 0;
+
+// Allow every filtering-kernel instance the whole LDS (once per process; before any graph capture).
+mdn_status init_walk_kernels() {
+    if (g_walk_init) return MDN_OK;
+    const void* fns[] = {(const void*)k_walk<_Float16, _Float16, _Float16>, (const void*)k_walk<float, _Float16, float>,
+                         (const void*)k_walk<float, float, float>, (const void*)k_walk<_Float16, float, _Float16>};
+    for (const void* f : fns)
+        if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess)
+            return fail(MDN_EDEVICE, "walk: cannot reserve LDS");
+    g_walk_init = 1;
+    return MDN_OK;
 }
 
 template <typename TZ, typename TU, typename TO>
 static mdn_status launch_typed_walk(const WalkArgs& a, int grid, size_t lds, hipStream_t st) {
-    static int attr_done = 0;
-    if (!attr_done) {
-        if (hipFuncSetAttribute((const void*)k_walk<TZ, TU, TO>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                160 * 1024) != hipSuccess)
-            return fail(MDN_EDEVICE, "walk: cannot reserve LDS");
-        attr_done = 1;
-    }
+    mdn_status e = init_walk_kernels();
+    if (e) return e;
     k_walk<TZ, TU, TO><<<grid, 64 * kWaves, lds, st>>>(a);
     return check_launch("walk");
+}
+
+mdn_status launch_walk_args(const WalkArgs& a, int zd, int ud, int od, hipStream_t st) {
+    if (a.n_strips <= 0) return MDN_OK;
+    const size_t lds = walk_lds_bytes(a.K);
+    const int ncu = device_cus();
+    const int blocks = (a.n_strips + kWaves - 1) / kWaves;
+    const int grid = blocks < ncu ? blocks : ncu;
+    const bool zh = zd == MDN_F16, uh = ud == MDN_F16, oh = od == MDN_F16;
+    if (zh && uh && oh) return launch_typed_walk<_Float16, _Float16, _Float16>(a, grid, lds, st);
+    if (!zh && uh && !oh) return launch_typed_walk<float, _Float16, float>(a, grid, lds, st);
+    if (!zh && !uh && !oh) return launch_typed_walk<float, float, float>(a, grid, lds, st);
+    if (zh && !uh && oh) return launch_typed_walk<_Float16, float, _Float16>(a, grid, lds, st);
+    return fail(MDN_ENOTSUP, "walk: input/coarse/output dtype combination not supported");
 }
 
 // Selection pass (float64 tensor, uint8 map) followed by the filtering pass.
@@ -379,28 +385,17 @@ mdn_status launch_walk(const mdn_image& z, const mdn_image& uc, const mdn_level&
     }
     WalkArgs a;
     memset(&a, 0, sizeof(a));
-    int dev = 0, ncu = 256;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     fill_walk_image(a.single, z, uc, out, 0);
     a.single.s_map = smap;
     a.single.s_pitch = s_pitch;
-    a.single.rows = walk_rows(z.width, z.height, ncu * kWaves);
+    a.single.rows = walk_rows(z.width, z.height, device_cus() * kWaves);
     a.imgs = nullptr;
     a.n_imgs = 1;
-    a.n_strips = walk_strips(z.width, z.height, a.single.rows);
+    a.n_strips = a.single.nsx * ((z.height + a.single.rows - 1) / a.single.rows);
     a.coeffs = lvl.coeffs;
     a.coeff_dtype = lvl.coeff_dtype;
     a.K = lvl.q_theta * lvl.q_s * lvl.q_c;
-    const size_t lds = walk_lds_bytes(a.K);
-    const int blocks = (a.n_strips + kWaves - 1) / kWaves;
-    const int grid = blocks < ncu ? blocks : ncu;
-    const bool zh = z.dtype == MDN_F16, uh = uc.dtype == MDN_F16, oh = out.dtype == MDN_F16;
-    if (zh && uh && oh) return launch_typed_walk<_Float16, _Float16, _Float16>(a, grid, lds, st);
-    if (!zh && uh && !oh) return launch_typed_walk<float, _Float16, float>(a, grid, lds, st);
-    if (!zh && !uh && !oh) return launch_typed_walk<float, float, float>(a, grid, lds, st);
-    if (zh && !uh && oh) return launch_typed_walk<_Float16, float, _Float16>(a, grid, lds, st);
-    return fail(MDN_ENOTSUP, "walk: input/coarse/output dtype combination not supported");
+    return launch_walk_args(a, z.dtype, uc.dtype, out.dtype, st);
 }
 
 }  // namespace mdn

@@ -1,0 +1,86 @@
+// Descriptor tables of the persistent column-walk kernels (pyramid, selection, filtering).
+// A launch walks a list of strips that may span many images: image i owns the strips
+// [strip_begin_i, strip_begin_i + nsx_i * ceil(height_i / rows_i)), found by binary search.
+#pragma once
+
+#include "mdn_internal.h"
+
+namespace mdn {
+
+constexpr int kWalkLanesOut = 58;   // filtering: output columns per wave (3-column halo each side)
+constexpr int kSelLanesOut = 58;    // selection: output columns per wave
+constexpr int kD2LanesOut = 60;     // pyramid: output columns per wave (2-column halo each side)
+
+struct WalkImage {
+    const void* z;          // RGB input of the level
+    const void* uc;         // coarser output (YCbCr, or RGB at the coarsest level)
+    void* out;
+    int64_t z_row, z_plane, uc_row, uc_plane, o_row, o_plane;
+    int32_t W, H, Wc, Hc;
+    int32_t z_dtype, uc_dtype, uc_rgb, o_dtype, o_rgb;
+    int32_t nsx;            // strips across
+    int32_t strip_begin;    // first strip index of this image in the list
+    int32_t rows;           // output rows per strip (a multiple of 14)
+    const uint8_t* s_map;   // selector of this level (from the selection pass)
+    int64_t s_pitch;
+};
+
+struct WalkArgs {
+    WalkImage single;           // used when imgs == nullptr
+    const WalkImage* imgs;      // device array (batch) or null
+    int32_t n_imgs, n_strips;
+    const void* coeffs;         // [K][3][98], float16 or float32
+    int32_t coeff_dtype, K;
+};
+
+struct SelImage {
+    const void* z;
+    uint8_t* s;
+    int64_t z_row, z_plane, s_pitch;
+    int32_t W, H, C;
+    int32_t nsx, strip_begin, rows;     // strips across, first strip, rows per strip (multiple of 10)
+};
+
+struct SelWalkArgs {
+    SelImage single;
+    const SelImage* imgs;
+    int32_t n_imgs, n_strips;
+    int32_t q_theta, q_s, q_c, half;
+    double s_lim[kMaxThr];      // 100 t^2: box sums of squared differences are 100 x the box mean
+    double c_k2[kMaxThr];       // (2t/(1+t^2))^2, or -1 when t <= 0 (always reached)
+    double bcos[kMaxTheta / 2], bsin[kMaxTheta / 2];
+};
+
+struct D2Image {
+    const void* in;
+    void* out;
+    int64_t i_row, i_plane, o_row, o_plane;
+    int32_t Wi, Hi, Wo, Ho;
+    int32_t nsx, strip_begin, rows;     // rows: output rows per strip (multiple of 4)
+    int32_t pad;
+};
+
+struct D2Args {
+    D2Image single;
+    const D2Image* imgs;
+    int32_t n_imgs, n_strips;
+};
+
+// strip heights chosen from the number of wave slots when not tuned
+int walk_rows(int w, int h, int wave_slots);
+int select_walk_rows(int w, int h, int ncu);
+int down2_rows(int wo, int ho, int ncu);
+
+void fill_walk_image(WalkImage& wi, const mdn_image& z, const mdn_image& uc, const mdn_image& out, int begin);
+void fill_sel_consts(const mdn_level& lvl, SelWalkArgs& a);
+size_t walk_lds_bytes(int K);
+int device_cus();
+
+mdn_status init_walk_kernels();
+
+// launches over prepared arguments (dtypes select the template instance)
+mdn_status launch_walk_args(const WalkArgs& a, int z_dtype, int uc_dtype, int o_dtype, hipStream_t st);
+mdn_status launch_select_args(const SelWalkArgs& a, int channels, int z_dtype, hipStream_t st);
+mdn_status launch_down2_args(const D2Args& a, int channels, int in_dtype, int out_dtype, hipStream_t st);
+
+}  // namespace mdn

@@ -1,0 +1,93 @@
+"""Batched form (one persistent launch per kernel and level over a ragged list of images, optional
+hipGraph replay): every image's output equals the plain per-image call bit for bit, alone or in
+the mix, eagerly or from repeated graph replays, before and after autotuning."""
+
+import numpy as np
+import pytest
+
+import synth
+from mdn_testlib import gpu_bank, trained_bank_multiscale
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [(1, 1), (3, 5), (57, 59), (130, 97), (481, 321), (200, 1500), (1024, 768), (64, 64)]
+
+
+def _setup(dtype=np.float16):
+    import torch
+    bank = trained_bank_multiscale(levels=3)
+    gb = gpu_bank(bank, 3, coeff_dtype=torch.float16)
+    zs = [torch.from_numpy(synth.noisy_pair(9000 + i, h, w, 3, 25, dtype=dtype)[0]).cuda()
+          for i, (h, w) in enumerate(SIZES)]
+    return gb, zs
+
+
+def _plain(M, gb, zs, storage):
+    return [M.denoise(z, gb, storage=storage).cpu().numpy() for z in zs]
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_equals_per_image(use_graph):
+    import torch
+    import paper_1802_06130_amd as M
+    gb, zs = _setup()
+    want = _plain(M, gb, zs, M.F16)
+    plan = M.Plan(gb, M.F16, max_images=16)
+    outs = [torch.empty_like(z) for z in zs]
+    for rep in range(3):
+        for o in outs:
+            o.fill_(-1.0)
+        plan.denoise_batch(zs, outs, use_graph=use_graph)
+        torch.cuda.synchronize()
+        got = [o.cpu().numpy() for o in outs]
+        for i, (g, w) in enumerate(zip(got, want)):
+            assert np.array_equal(g, w), f"replay {rep}, image {i} {SIZES[i]} differs"
+        _ = (zs[0] * 2).sum().item()          # unrelated eager work between replays
+    plan.close()
+
+
+def test_batch_alone_vs_mix_and_float32_io():
+    import torch
+    import paper_1802_06130_amd as M
+    gb, zs = _setup(np.float32)
+    plan = M.Plan(gb, M.F16, max_images=16)
+    mix = plan.denoise_batch(zs, use_graph=True)
+    torch.cuda.synchronize()
+    mix = [m.cpu().numpy() for m in mix]
+    for i, z in enumerate(zs):
+        alone = plan.denoise_batch([z], use_graph=False)[0].cpu().numpy()
+        assert np.array_equal(alone, mix[i]), f"image {i} differs alone vs in the mix"
+    plain = _plain(M, gb, zs, M.F16)
+    for i in range(len(zs)):
+        assert np.array_equal(plain[i], mix[i])
+    plan.close()
+
+
+def test_autotune_keeps_results():
+    import torch
+    import paper_1802_06130_amd as M
+    gb, zs = _setup()
+    want = _plain(M, gb, zs, M.F16)
+    plan = M.Plan(gb, M.F16, max_images=16)
+    rows = plan.autotune(zs)
+    print("tuned rows per level (pyramid, selection, filtering):", rows)
+    assert len(rows) == 3
+    for d2, se, wa in rows:
+        assert d2 in (8, 16, 32, 64) and se in (10, 20, 30, 60) and wa in (14, 28, 42, 56)
+    got = plan.denoise_batch(zs, use_graph=True)
+    torch.cuda.synchronize()
+    for g, w in zip(got, want):
+        assert np.array_equal(g.cpu().numpy(), w)
+    plan.close()
+
+
+def test_batch_rejects_bad_inputs():
+    import torch
+    import paper_1802_06130_amd as M
+    gb, zs = _setup()
+    plan = M.Plan(gb, M.F16, max_images=2)
+    with pytest.raises(M.MdnError):
+        plan.denoise_batch(zs[:3])                              # more than max_images
+    with pytest.raises(M.MdnError):
+        plan.denoise_batch([zs[2]], [torch.empty((3, 5, 5), dtype=torch.float16, device="cuda")])
+    plan.close()
