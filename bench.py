@@ -17,6 +17,13 @@ pairs at the same noise level, GPU equal-population thresholds, ridge 1e-3, floa
 before timing. A float32-storage run of the same batch (float32 filters, float32 arithmetic) is
 reported beside it.
 
+The served form replays open-loop Poisson request traces (2,000 requests at each of 50, 200 and
+800 requests/s, arrival seed 5000 + rate) through the library's serving loop: sizes uniform over
+{1280x720, 1920x1080, 4032x3024}, noise sigma uniform over {15, 25, 50}/255 selecting one of three
+GPU-trained banks, float16 host images in pinned memory, results copied back into per-slot pinned
+staging buffers. It reports p50/p99 latency (arrival to device done, arrival to host done) and
+completed megapixels/s beside the offered load. Its latencies include both PCIe copies.
+
 Prints one JSON line. Run: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
 
@@ -66,8 +73,8 @@ def make_inputs(n: int, dtype):
     return sizes, imgs
 
 
-def train_bank(M, torch, n_pairs=32, size=256):
-    pairs = [synth.noisy_pair(7000 + i, size, size, 3, SIGMA) for i in range(n_pairs)]
+def train_bank(M, torch, n_pairs=32, size=256, sigma=SIGMA):
+    pairs = [synth.noisy_pair(7000 + i, size, size, 3, sigma) for i in range(n_pairs)]
     dev = torch.device("cuda:0")
     pairs = [(torch.from_numpy(z).to(dev), torch.from_numpy(u).to(dev)) for z, u in pairs]
     bank, _, fbs = M.train_multiscale(pairs, LEVELS, Q_THETA, Q_S, Q_C, RADIUS, RADIUS, 1e-3)
@@ -135,6 +142,73 @@ def run_batched(M, torch, zs, bank, steps, warmup):
     lat = np.array([a.elapsed_time(b) for a, b in evs])
     plan.close()
     return wall, lat, rows, outs
+
+
+SERVE_SIZES = [(1280, 720), (1920, 1080), (4032, 3024)]
+SERVE_SIGMAS = [15.0, 25.0, 50.0]
+
+
+def _make_serve_image(args):
+    k, w, h, sigma = args
+    z, _ = synth.noisy_pair(8100 + k, h, w, 3, sigma, dtype=np.float16)
+    return z
+
+
+def run_served(M, torch, banks16, rates, n_requests):
+    """Open-loop Poisson traces through the serving loop; returns the per-rate report."""
+    jobs = [(3 * si + gi, w, h, g) for si, (w, h) in enumerate(SERVE_SIZES) for gi, g in enumerate(SERVE_SIGMAS)]
+    workers = max(1, min(9, len(os.sched_getaffinity(0))))
+    with mp.get_context("fork").Pool(workers) as pool:
+        imgs = pool.map(_make_serve_image, jobs, chunksize=1)
+    host = [torch.from_numpy(z).pin_memory() for z in imgs]          # [size * 3 + sigma]
+    staging = max(z.numel() for z in host) * 2
+    srv = M.Server(banks16, storage=M.F16, max_slots=16, stages_per_tick=1, max_ticks_in_flight=2,
+                   hbm_budget=8 << 30, staging_bytes=staging)
+    px_of = [w * h for w, h in SERVE_SIZES]
+    # latency of each size alone (no other request in the server)
+    alone = {}
+    for si, (w, h) in enumerate(SERVE_SIZES):
+        lat = []
+        for rep in range(4):
+            srv.submit(host[si * 3 + 1], 1, None, tag=rep)
+            (c,) = srv.wait_all()
+            lat.append((c["t_host_done"] - c["t_arrival"]) * 1e3)
+        alone[f"{w}x{h}"] = round(float(np.median(lat[1:])), 3)
+    report = {"alone_host_ms": alone}
+    for rate in rates:
+        rng = np.random.default_rng(5000 + rate)
+        arrivals = synth.poisson_arrivals(float(rate), n_requests, 5000 + rate)
+        size = rng.integers(0, 3, n_requests)
+        sig = rng.integers(0, 3, n_requests)
+        reqs = [M.Server.request(host[int(a) * 3 + int(b)], int(b)) for a, b in zip(size, sig)]
+        before = srv.stats()
+        t0 = time.perf_counter()
+        done = srv.replay(reqs, arrivals)
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        ok = [c for c in done if c["status"] == M.MDN_OK]
+        px = np.array([px_of[s] for s, c in zip(size, done) if c["status"] == M.MDN_OK], dtype=np.float64)
+        dev = np.array([(c["t_device_done"] - c["t_arrival"]) * 1e3 for c in ok])
+        hst = np.array([(c["t_host_done"] - c["t_arrival"]) * 1e3 for c in ok])
+        span = max(c["t_host_done"] for c in ok) - min(c["t_arrival"] for c in done)
+        ticks = st["ticks"] - before["ticks"]
+        report[str(rate)] = {
+            "requests": n_requests, "completed": len(ok), "failed_or_rejected": n_requests - len(ok),
+            "offered_MP_s": round(float(sum(px_of[s] for s in size) / 1e6 / arrivals[-1]), 1),
+            "completed_MP_s": round(float(px.sum() / 1e6 / span), 1),
+            "device_done_ms": {"p50": round(float(np.percentile(dev, 50)), 3),
+                               "p99": round(float(np.percentile(dev, 99)), 3)},
+            "host_done_ms": {"p50": round(float(np.percentile(hst, 50)), 3),
+                             "p99": round(float(np.percentile(hst, 99)), 3)},
+            "ticks": int(ticks), "launches": int(st["launches"] - before["launches"]),
+            "stages_per_tick_mean": round((st["tick_items"] - before["tick_items"]) / max(1, ticks), 2),
+            "wall_s": round(wall, 2)}
+        print(f"# served {rate} req/s: {report[str(rate)]}", file=sys.stderr, flush=True)
+    report["config"] = ("16 slots, 8 GiB device budget, 1 stage per tick, 2 ticks ahead; sizes uniform over "
+                        "1280x720/1920x1080/4032x3024, sigma uniform over 15/25/50 of 255 (one bank each), "
+                        "float16 pinned host images, Poisson arrivals seed 5000+rate")
+    srv.close()
+    return report
 
 
 def time_level0_filter(M, torch, zs, bank, n=16, reps=3):
@@ -240,6 +314,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f32", action="store_true")
     ap.add_argument("--pmc-probe", action="store_true", help="run only the hardware-counter probe")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=2000)
     args = ap.parse_args()
     if args.pmc_probe:
         pmc_probe()
@@ -330,6 +406,14 @@ def main():
     }
     if f32 is not None:
         line["plain_f32"] = f32
+    if not args.no_serve:
+        del zs
+        torch.cuda.empty_cache()
+        banks = []
+        for g in SERVE_SIGMAS:
+            b32 = bank32 if g == SIGMA else train_bank(M, torch, sigma=g)[0]
+            banks.append(as_dtype(M, b32, torch.float16))
+        line["served"] = run_served(M, torch, banks, (50, 200, 800), args.serve_requests)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(imgs, bank32)
     print(json.dumps(line), flush=True)

@@ -36,7 +36,9 @@ typedef enum {
     MDN_EINVAL = 1,   /* bad argument: null pointer, size mismatch, unknown enum */
     MDN_ENOMEM = 2,   /* workspace too small */
     MDN_EDEVICE = 3,  /* HIP launch or runtime error */
-    MDN_ENOTSUP = 4   /* valid but unsupported configuration (filter radius, K > 255, ...) */
+    MDN_ENOTSUP = 4,  /* valid but unsupported configuration (filter radius, K > 255, ...) */
+    MDN_ETIMEOUT = 5, /* serving: the request waited longer than the queue time-out */
+    MDN_ECANCELED = 6 /* serving: the request was cancelled */
 } mdn_status;
 
 typedef enum { MDN_F32 = 0, MDN_F16 = 1 } mdn_dtype;
@@ -234,6 +236,117 @@ mdn_status mdn_plan_autotune(mdn_plan* plan, const mdn_image* in, const mdn_imag
  * replayed afterwards. Ordered after prior work on `stream` and before later work. */
 mdn_status mdn_denoise_batch(mdn_plan* plan, const mdn_image* in, const mdn_image* out, int32_t n,
                              int32_t use_graph, void* stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Serving loop (host code above the calls of this header): requests of any sizes arrive over
+ * time, each naming one of several device-resident banks (one per noise level, which is taken
+ * as known, Section 5). A request is admitted when a slot is free and its device footprint
+ * (input, output, pyramid levels, selector map) fits the memory budget, first come first served
+ * with no overtaking. Its input is copied to the device on a copy stream; it then joins the next
+ * scheduling tick. A tick advances every active request by up to stages_per_tick cascade stages
+ * (pyramid levels 0..L-1, then selection and filtering of levels L-1..0, Section 4) with one
+ * persistent launch per kernel, level, bank and dtype over all requests at that point, so a
+ * request that arrives while others are mid-cascade shares their next launches. Ticks queue on
+ * one compute stream, at most max_ticks_in_flight ahead of the device; each result is copied back
+ * on a second copy stream once the tick holding its last stage is done. A request's output is
+ * bitwise the same whatever it was batched with, and the same as mdn_denoise's.
+ *
+ * Threads: mdn_server_submit, mdn_server_cancel and mdn_server_stats may be called from any
+ * thread; mdn_server_poll, mdn_server_replay and mdn_server_destroy from one thread at a time.
+ * --------------------------------------------------------------------------------------- */
+typedef struct mdn_server mdn_server;
+
+typedef enum { MDN_EXEC_HIP = 0, MDN_EXEC_FAKE = 1 } mdn_executor_kind;
+
+typedef struct mdn_server_config {
+    const mdn_bank* banks;        /* n_banks float16 7x7/7x7 colour banks (K <= 243 per level); the
+                                     descriptors and thresholds are copied, the coefficient buffers
+                                     must stay valid while the server lives */
+    int32_t n_banks;              /* 1..16 */
+    int32_t storage;              /* pyramid dtype (float16 requests need MDN_F16) */
+    int32_t max_slots;            /* requests admitted at once, 1..256 */
+    int32_t stages_per_tick;      /* >= 1 */
+    int32_t max_ticks_in_flight;  /* 1..8 */
+    int32_t executor;             /* mdn_executor_kind */
+    int32_t reserved[2];          /* must be zero */
+    uint64_t hbm_budget;          /* device bytes for admitted requests, allocated once at creation */
+    uint64_t staging_bytes;       /* pinned host bytes per slot for requests without host_out (0: none) */
+    double queue_timeout;         /* seconds a request may wait for admission; <= 0: no limit */
+    /* MDN_EXEC_FAKE only: virtual-clock cost model (0 or negative: defaults 25, 25, 20, 5) */
+    double fake_h2d_gbps, fake_d2h_gbps, fake_gpx_per_s, fake_launch_us;
+} mdn_server_config;
+
+typedef struct mdn_request {
+    const void* host_in;   /* planar RGB [3][height][width] in dtype, [0,1] scale; read until the
+                              request's upload is done (pinned memory gives asynchronous copies) */
+    void* host_out;        /* same layout and dtype, or NULL: the slot's staging buffer */
+    int32_t width, height;
+    int32_t dtype;         /* MDN_F16 or MDN_F32 */
+    int32_t bank;          /* index into the server's banks */
+    uint64_t tag;          /* caller's, returned in the completion (replay: ignored) */
+} mdn_request;
+
+typedef struct mdn_completion {
+    uint64_t id, tag;
+    int32_t status;        /* MDN_OK, MDN_EDEVICE, MDN_ETIMEOUT, MDN_ECANCELED, or the rejection */
+    int32_t slot;          /* slot held while admitted (-1 if never admitted) */
+    int32_t tick_first, tick_last;   /* ticks that ran its first and last stages (-1: none) */
+    /* seconds on the server clock (negative: did not happen); device_done is when the host saw
+       the tick with the last stage finish, host_done when it saw the copy back finish */
+    double t_arrival, t_admit, t_device_done, t_host_done;
+    void* host_out;        /* where the result is, NULL unless status is MDN_OK; a slot's staging
+                              buffer stays valid until the next mdn_server_poll call (replay
+                              reuses staging buffers at once: give host_out to keep results) */
+} mdn_completion;
+
+typedef struct mdn_server_stats {
+    uint64_t submitted, admitted, completed, failed, rejected;
+    uint64_t ticks, launches, tick_items;    /* tick_items: stages issued over all ticks */
+    uint64_t arena_bytes, arena_used, arena_peak;
+    int32_t queued, active;
+} mdn_server_counters;
+
+/* Create a server; with MDN_EXEC_HIP it allocates the budget, the tables, the staging buffers and
+ * three streams (default priority) on the current device. */
+mdn_status mdn_server_create(const mdn_server_config* cfg, mdn_server** server);
+/* Wait for enqueued device work, then free everything; requests still queued or running are
+ * dropped without completions. */
+mdn_status mdn_server_destroy(mdn_server* server);
+
+/* Queue a request (arrival time = now). Rejected at once, with nothing queued, when invalid
+ * (MDN_EINVAL / MDN_ENOTSUP) or when its footprint exceeds the whole budget (MDN_ENOMEM). */
+mdn_status mdn_server_submit(mdn_server* server, const mdn_request* req, uint64_t* id);
+/* Cancel by id: a waiting request completes with MDN_ECANCELED at the next poll; a running one
+ * stops being scheduled and completes with MDN_ECANCELED once its work in flight is done; one
+ * whose last stage is already issued completes normally. */
+mdn_status mdn_server_cancel(mdn_server* server, uint64_t id);
+/* Advance the schedule for up to max_wait seconds (virtual seconds with MDN_EXEC_FAKE) or until a
+ * completion is ready or nothing is left, then return up to max_out completions. */
+mdn_status mdn_server_poll(mdn_server* server, double max_wait, mdn_completion* out, int32_t max_out,
+                           int32_t* n_out);
+/* Open-loop trace: request i is submitted at arrival[i] seconds after the call (non-decreasing)
+ * by an arrival thread while the calling thread runs the schedule; returns when all n are
+ * complete, out[i] being request i's completion (rejections included). Needs an idle server. */
+mdn_status mdn_server_replay(mdn_server* server, const mdn_request* reqs, const double* arrival, int32_t n,
+                             mdn_completion* out);
+mdn_status mdn_server_stats(mdn_server* server, mdn_server_counters* out);
+mdn_status mdn_server_now(mdn_server* server, double* seconds);
+/* Device bytes the request would hold while admitted: input and output (each rounded up to 256
+ * bytes) plus its pyramid levels (rows padded to 64 elements) and selector map. */
+mdn_status mdn_server_footprint(mdn_server* server, const mdn_request* req, uint64_t* bytes);
+
+/* MDN_EXEC_FAKE only: move the virtual clock forward to t, and force failures or delays on the
+ * request with the given tag (upload, launch, asynchronous tick failure, copy back, or a stall of
+ * `value` seconds added to the tick that holds its next stage). */
+typedef enum {
+    MDN_FAKE_FAIL_UPLOAD = 0,
+    MDN_FAKE_FAIL_LAUNCH = 1,
+    MDN_FAKE_FAIL_TICK = 2,
+    MDN_FAKE_FAIL_DOWNLOAD = 3,
+    MDN_FAKE_STALL = 4
+} mdn_fake_injection;
+mdn_status mdn_server_fake_advance(mdn_server* server, double t);
+mdn_status mdn_server_fake_inject(mdn_server* server, int32_t what, uint64_t tag, double value);
 
 /* Thread-local description of the last non-OK status (empty string if none). */
 const char* mdn_last_error(void);

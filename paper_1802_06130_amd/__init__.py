@@ -8,4 +8,6 @@ from ._lib import (  # noqa: F401
     pyramid_build, select_filters,
     GRAM_BF16X3, GRAM_F32, X_CROSS_CHANNEL, X_PER_CHANNEL, Gram, level_features, level_thresholds,
     quantiles, train_accumulate, train_multiscale, train_single, train_solve, Plan,
+    EXEC_FAKE, EXEC_HIP, FAKE_FAIL_DOWNLOAD, FAKE_FAIL_LAUNCH, FAKE_FAIL_TICK, FAKE_FAIL_UPLOAD, FAKE_STALL,
+    MDN_ECANCELED, MDN_EDEVICE, MDN_EINVAL, MDN_ENOMEM, MDN_ENOTSUP, MDN_ETIMEOUT, MDN_OK, Server,
 )

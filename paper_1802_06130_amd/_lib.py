@@ -18,10 +18,10 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libmdn.so")
 HEADER_PATH = os.path.join(os.path.dirname(_PKG), "include", "mdn.h")
 
-MDN_OK, MDN_EINVAL, MDN_ENOMEM, MDN_EDEVICE, MDN_ENOTSUP = range(5)
+MDN_OK, MDN_EINVAL, MDN_ENOMEM, MDN_EDEVICE, MDN_ENOTSUP, MDN_ETIMEOUT, MDN_ECANCELED = range(7)
 F32, F16 = 0, 1
 GRAY, RGB, YCC = 0, 1, 2
-_STATUS = {1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOTSUP"}
+_STATUS = {1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOTSUP", 5: "ETIMEOUT", 6: "ECANCELED"}
 
 
 class MdnError(RuntimeError):
@@ -475,6 +475,180 @@ class Plan:
     def close(self):
         if getattr(self, "handle", None):
             lib().mdn_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ----------------------------------------------------------------------------- serving loop
+
+EXEC_HIP, EXEC_FAKE = 0, 1
+FAKE_FAIL_UPLOAD, FAKE_FAIL_LAUNCH, FAKE_FAIL_TICK, FAKE_FAIL_DOWNLOAD, FAKE_STALL = range(5)
+
+
+class MdnServerConfig(ct.Structure):
+    _fields_ = [("banks", ct.POINTER(MdnBank)), ("n_banks", ct.c_int32), ("storage", ct.c_int32),
+                ("max_slots", ct.c_int32), ("stages_per_tick", ct.c_int32),
+                ("max_ticks_in_flight", ct.c_int32), ("executor", ct.c_int32), ("reserved", ct.c_int32 * 2),
+                ("hbm_budget", ct.c_uint64), ("staging_bytes", ct.c_uint64), ("queue_timeout", ct.c_double),
+                ("fake_h2d_gbps", ct.c_double), ("fake_d2h_gbps", ct.c_double),
+                ("fake_gpx_per_s", ct.c_double), ("fake_launch_us", ct.c_double)]
+
+
+class MdnRequest(ct.Structure):
+    _fields_ = [("host_in", ct.c_void_p), ("host_out", ct.c_void_p), ("width", ct.c_int32),
+                ("height", ct.c_int32), ("dtype", ct.c_int32), ("bank", ct.c_int32), ("tag", ct.c_uint64)]
+
+
+class MdnCompletion(ct.Structure):
+    _fields_ = [("id", ct.c_uint64), ("tag", ct.c_uint64), ("status", ct.c_int32), ("slot", ct.c_int32),
+                ("tick_first", ct.c_int32), ("tick_last", ct.c_int32), ("t_arrival", ct.c_double),
+                ("t_admit", ct.c_double), ("t_device_done", ct.c_double), ("t_host_done", ct.c_double),
+                ("host_out", ct.c_void_p)]
+
+
+class MdnServerCounters(ct.Structure):
+    _fields_ = [(n, ct.c_uint64) for n in ("submitted", "admitted", "completed", "failed", "rejected", "ticks",
+                                          "launches", "tick_items", "arena_bytes", "arena_used", "arena_peak")] + \
+               [("queued", ct.c_int32), ("active", ct.c_int32)]
+
+
+def _server_sigs(L):
+    vp, i32, u64, dbl = ct.c_void_p, ct.c_int32, ct.c_uint64, ct.c_double
+    P = ct.POINTER
+    sig = {
+        "mdn_server_create": [P(MdnServerConfig), P(vp)],
+        "mdn_server_destroy": [vp],
+        "mdn_server_submit": [vp, P(MdnRequest), P(u64)],
+        "mdn_server_cancel": [vp, u64],
+        "mdn_server_poll": [vp, dbl, P(MdnCompletion), i32, P(i32)],
+        "mdn_server_replay": [vp, P(MdnRequest), P(dbl), i32, P(MdnCompletion)],
+        "mdn_server_stats": [vp, P(MdnServerCounters)],
+        "mdn_server_now": [vp, P(dbl)],
+        "mdn_server_footprint": [vp, P(MdnRequest), P(u64)],
+        "mdn_server_fake_advance": [vp, dbl],
+        "mdn_server_fake_inject": [vp, i32, u64, dbl],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = ct.c_int
+
+
+def _completion(c: MdnCompletion) -> dict:
+    return {k: getattr(c, k) for k, _ in MdnCompletion._fields_}
+
+
+class Server:
+    """Serving loop over several banks (one per noise level): admission by device footprint,
+    continuous batching of cascade stages, copies on their own streams. Host images are
+    (3, H, W) contiguous CPU tensors (pinned for asynchronous copies)."""
+
+    def __init__(self, banks: List[Bank], storage: int = F16, max_slots: int = 16, stages_per_tick: int = 1,
+                 max_ticks_in_flight: int = 2, hbm_budget: int = 4 << 30, staging_bytes: int = 0,
+                 queue_timeout: float = 0.0, executor: int = EXEC_HIP, fake_model=(25.0, 25.0, 20.0, 5.0)):
+        _server_sigs(lib())
+        self.banks = list(banks)               # keeps the coefficient tensors alive
+        descs = [b.desc() for b in self.banks]
+        self._bank_arr = (MdnBank * len(descs))(*descs)
+        cfg = MdnServerConfig()
+        cfg.banks = ct.cast(self._bank_arr, ct.POINTER(MdnBank))
+        cfg.n_banks = len(descs)
+        cfg.storage = storage
+        cfg.max_slots = max_slots
+        cfg.stages_per_tick = stages_per_tick
+        cfg.max_ticks_in_flight = max_ticks_in_flight
+        cfg.executor = executor
+        cfg.hbm_budget = hbm_budget
+        cfg.staging_bytes = staging_bytes
+        cfg.queue_timeout = queue_timeout
+        cfg.fake_h2d_gbps, cfg.fake_d2h_gbps, cfg.fake_gpx_per_s, cfg.fake_launch_us = fake_model
+        h = ct.c_void_p()
+        _check(lib().mdn_server_create(ct.byref(cfg), ct.byref(h)))
+        self.handle = h
+        self._held = {}
+
+    @staticmethod
+    def request(host_in, bank: int, host_out=None, tag: int = 0) -> MdnRequest:
+        if host_in.dim() != 3 or host_in.shape[0] != 3 or not host_in.is_contiguous():
+            raise ValueError("host images are contiguous (3, H, W)")
+        if host_out is not None and (host_out.shape != host_in.shape or host_out.dtype != host_in.dtype
+                                     or not host_out.is_contiguous()):
+            raise ValueError("host_out must match host_in")
+        _, H, W = host_in.shape
+        return MdnRequest(host_in.data_ptr(), host_out.data_ptr() if host_out is not None else None,
+                          W, H, _dtype_code(host_in), bank, tag)
+
+    def submit(self, host_in, bank: int, host_out=None, tag: int = 0) -> int:
+        rid = ct.c_uint64()
+        _check(lib().mdn_server_submit(self.handle, ct.byref(self.request(host_in, bank, host_out, tag)),
+                                       ct.byref(rid)))
+        self._held[rid.value] = (host_in, host_out)
+        return rid.value
+
+    def submit_request(self, req: MdnRequest) -> int:
+        """Submit a prepared descriptor (the caller keeps its host buffers alive)."""
+        rid = ct.c_uint64()
+        _check(lib().mdn_server_submit(self.handle, ct.byref(req), ct.byref(rid)))
+        return rid.value
+
+    def footprint(self, req: MdnRequest) -> int:
+        b = ct.c_uint64()
+        _check(lib().mdn_server_footprint(self.handle, ct.byref(req), ct.byref(b)))
+        return b.value
+
+    def cancel(self, rid: int):
+        _check(lib().mdn_server_cancel(self.handle, rid))
+
+    def poll(self, max_wait: float = 0.0, max_out: int = 256) -> List[dict]:
+        out = (MdnCompletion * max_out)()
+        n = ct.c_int32()
+        _check(lib().mdn_server_poll(self.handle, max_wait, out, max_out, ct.byref(n)))
+        res = [_completion(out[i]) for i in range(n.value)]
+        for c in res:
+            self._held.pop(c["id"], None)
+        return res
+
+    def wait_all(self, max_wait: float = 1e9) -> List[dict]:
+        done = []
+        while True:
+            got = self.poll(max_wait)
+            done += got
+            st = self.stats()
+            if not got and st["queued"] == 0 and st["active"] == 0:
+                return done
+
+    def replay(self, requests: Sequence[MdnRequest], arrivals: Sequence[float]) -> List[dict]:
+        n = len(requests)
+        reqs = (MdnRequest * n)(*requests)
+        arr = (ct.c_double * n)(*[float(a) for a in arrivals])
+        out = (MdnCompletion * n)()
+        _check(lib().mdn_server_replay(self.handle, reqs, arr, n, out))
+        return [_completion(out[i]) for i in range(n)]
+
+    def stats(self) -> dict:
+        c = MdnServerCounters()
+        _check(lib().mdn_server_stats(self.handle, ct.byref(c)))
+        return {k: getattr(c, k) for k, _ in MdnServerCounters._fields_}
+
+    def now(self) -> float:
+        t = ct.c_double()
+        _check(lib().mdn_server_now(self.handle, ct.byref(t)))
+        return t.value
+
+    def fake_advance(self, t: float):
+        _check(lib().mdn_server_fake_advance(self.handle, t))
+
+    def fake_inject(self, what: int, tag: int, value: float = 0.0):
+        _check(lib().mdn_server_fake_inject(self.handle, what, tag, value))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().mdn_server_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -16,8 +16,6 @@ using namespace mdn;
 
 namespace {
 
-constexpr int kMaxLevels = 8;
-
 size_t al256(size_t v) { return (v + 255) / 256 * 256; }
 int64_t pitch64(int w) { return ((int64_t)w + 63) / 64 * 64; }
 
@@ -71,13 +69,7 @@ struct mdn_plan {
     bool tables_valid = false;
     int rows_d2[kMaxLevels], rows_sel[kMaxLevels], rows_walk[kMaxLevels];
     bool tuned = false;
-    // prepared launch arguments (tables point into tab_dev)
-    D2Args d2[kMaxLevels];
-    SelWalkArgs sel[kMaxLevels];
-    WalkArgs walk[kMaxLevels];
-    int in_dtype = MDN_F16, out_dtype = MDN_F16;
-    std::vector<mdn_image> zl, ul;      // [image * (L+1) + level]
-    std::vector<uint8_t*> smap;
+    BatchLaunch bl;                     // prepared launch arguments (tables in tab_dev)
 };
 
 namespace {
@@ -128,70 +120,107 @@ mdn_status ensure_tables(mdn_plan* p, size_t need) {
     return MDN_OK;
 }
 
-// Carve the per-image pyramids out of the workspace and build the launch tables for `n` images.
-mdn_status prepare(mdn_plan* p, const mdn_image* in, const mdn_image* out, int n) {
-    const int L = p->L;
-    size_t need = 0;
-    for (int i = 0; i < n; ++i) need += image_ws(in[i].width, in[i].height, L, p->storage) + al256((size_t)in[i].width * in[i].height);
-    mdn_status st;
-    if ((st = ensure_ws(p, need))) return st;
-    const size_t tab_need = al256(sizeof(D2Image) * n) * L + al256(sizeof(SelImage) * n) * L + al256(sizeof(WalkImage) * n) * L;
-    if ((st = ensure_tables(p, tab_need))) return st;
-    if (hipStreamSynchronize(p->stream) != hipSuccess) return fail(MDN_EDEVICE, "plan: sync failed");
+}  // namespace
 
-    p->zl.assign((size_t)n * (L + 1), mdn_image{});
-    p->ul.assign((size_t)n * (L + 1), mdn_image{});
-    p->smap.assign(n, nullptr);
-    char* w = p->ws;
-    for (int i = 0; i < n; ++i) {
-        int W = in[i].width, H = in[i].height;
-        p->zl[(size_t)i * (L + 1)] = in[i];
-        for (int l = 1; l <= L; ++l) {
-            W = (W + 1) / 2;
-            H = (H + 1) / 2;
-            const size_t b = al256((size_t)pitch64(W) * H * 3 * (p->storage == MDN_F16 ? 2 : 4));
-            p->zl[(size_t)i * (L + 1) + l] = mk_image(w, W, H, p->storage, MDN_RGB);
+namespace mdn {
+
+size_t batch_image_ws(int w, int h, int L, int storage) { return image_ws(w, h, L, storage) + al256((size_t)w * h); }
+
+size_t batch_table_bytes(int n, int L) {
+    return al256(sizeof(D2Image) * n) * L + al256(sizeof(SelImage) * n) * L + al256(sizeof(WalkImage) * n) * L;
+}
+
+// Per-level descriptors of one image's cascade, each with strip_begin = 0: d2[l] makes z^{l+1}
+// from z^l, sel[l] and walk[l] run level l (walk[0] writes `out`). ws (batch_image_ws bytes,
+// 256-aligned) holds z^1..z^L, u^1..u^{L-1} and the selector map, which every level reuses.
+void describe_cascade(const mdn_image& in, const mdn_image& out, void* ws, int L, int storage, const int (*rows)[3],
+                      int ncu, D2Image* d2, SelImage* sel, WalkImage* walk) {
+    mdn_image zl[kMaxLevels + 1], ul[kMaxLevels + 1];
+    char* w = static_cast<char*>(ws);
+    int W = in.width, H = in.height;
+    zl[0] = in;
+    ul[0] = out;
+    for (int l = 1; l <= L; ++l) {
+        W = (W + 1) / 2;
+        H = (H + 1) / 2;
+        const size_t b = al256((size_t)pitch64(W) * H * 3 * (storage == MDN_F16 ? 2 : 4));
+        zl[l] = mk_image(w, W, H, storage, MDN_RGB);
+        w += b;
+        if (l < L) {
+            ul[l] = mk_image(w, W, H, storage, MDN_YCC);
             w += b;
-            if (l < L) {
-                p->ul[(size_t)i * (L + 1) + l] = mk_image(w, W, H, p->storage, MDN_YCC);
-                w += b;
-            }
         }
-        p->smap[i] = reinterpret_cast<uint8_t*>(w);
-        w += al256((size_t)in[i].width * in[i].height);
-        p->ul[(size_t)i * (L + 1)] = out[i];
     }
+    uint8_t* smap = reinterpret_cast<uint8_t*>(w);
+    for (int l = 0; l < L; ++l) {
+        const mdn_image& a = zl[l];
+        const mdn_image& o = zl[l + 1];
+        D2Image& d = d2[l];
+        memset(&d, 0, sizeof(d));
+        d.in = a.data;
+        d.out = o.data;
+        d.i_row = a.row_pitch;
+        d.i_plane = a.plane_pitch;
+        d.o_row = o.row_pitch;
+        d.o_plane = o.plane_pitch;
+        d.Wi = a.width;
+        d.Hi = a.height;
+        d.Wo = o.width;
+        d.Ho = o.height;
+        d.nsx = (o.width + kD2LanesOut - 1) / kD2LanesOut;
+        d.rows = rows ? rows[l][0] : down2_rows(o.width, o.height, ncu);
 
+        SelImage& e = sel[l];
+        memset(&e, 0, sizeof(e));
+        e.z = a.data;
+        e.s = smap;
+        e.z_row = a.row_pitch;
+        e.z_plane = a.plane_pitch;
+        e.s_pitch = a.width;
+        e.W = a.width;
+        e.H = a.height;
+        e.C = 3;
+        e.nsx = (a.width + kSelLanesOut - 1) / kSelLanesOut;
+        e.rows = rows ? rows[l][1] : select_walk_rows(a.width, a.height, ncu);
+
+        fill_walk_image(walk[l], a, l == L - 1 ? zl[L] : ul[l + 1], ul[l], 0);
+        walk[l].s_map = smap;
+        walk[l].s_pitch = a.width;
+        walk[l].rows = rows ? rows[l][2] : walk_rows(a.width, a.height, ncu * 4);
+    }
+}
+
+int strips_of(const D2Image& d) { return d.nsx * ((d.Ho + d.rows - 1) / d.rows); }
+int strips_of(const SelImage& d) { return d.nsx * ((d.H + d.rows - 1) / d.rows); }
+int strips_of(const WalkImage& d) { return d.nsx * ((d.H + d.rows - 1) / d.rows); }
+
+// Launch tables of one batch: image i uses the workspace ws[i] (batch_image_ws bytes, 256-aligned).
+// Tables go to tab_host (pinned) and are meant to be copied to tab_dev before the launches.
+// rows: per level {pyramid, selection, filtering} strip heights, or null for the defaults.
+mdn_status build_batch(const mdn_level* lv, const SelWalkArgs* selc, int L, int storage, const mdn_image* in,
+                       const mdn_image* out, void* const* ws, int n, const int (*rows)[3], char* tab_host,
+                       char* tab_dev, BatchLaunch* bl) {
     const int ncu = device_cus();
-    char* th = p->tab_host;
-    char* td = p->tab_dev;
+    std::vector<D2Image> d2((size_t)n * L);
+    std::vector<SelImage> sel((size_t)n * L);
+    std::vector<WalkImage> walk((size_t)n * L);
+    for (int i = 0; i < n; ++i)
+        describe_cascade(in[i], out[i], ws[i], L, storage, rows, ncu, &d2[(size_t)i * L], &sel[(size_t)i * L],
+                         &walk[(size_t)i * L]);
+    char* th = tab_host;
+    char* td = tab_dev;
     for (int l = 0; l < L; ++l) {
         D2Image* t = reinterpret_cast<D2Image*>(th);
         int begin = 0;
         for (int i = 0; i < n; ++i) {
-            const mdn_image& a = p->zl[(size_t)i * (L + 1) + l];
-            const mdn_image& b = p->zl[(size_t)i * (L + 1) + l + 1];
-            D2Image& d = t[i];
-            memset(&d, 0, sizeof(d));
-            d.in = a.data;
-            d.out = b.data;
-            d.i_row = a.row_pitch;
-            d.i_plane = a.plane_pitch;
-            d.o_row = b.row_pitch;
-            d.o_plane = b.plane_pitch;
-            d.Wi = a.width;
-            d.Hi = a.height;
-            d.Wo = b.width;
-            d.Ho = b.height;
-            d.nsx = (b.width + kD2LanesOut - 1) / kD2LanesOut;
-            d.rows = p->tuned ? p->rows_d2[l] : down2_rows(b.width, b.height, ncu);
-            d.strip_begin = begin;
-            begin += d.nsx * ((b.height + d.rows - 1) / d.rows);
+            t[i] = d2[(size_t)i * L + l];
+            t[i].strip_begin = begin;
+            begin += strips_of(t[i]);
         }
-        memset(&p->d2[l], 0, sizeof(D2Args));
-        p->d2[l].imgs = reinterpret_cast<const D2Image*>(td);
-        p->d2[l].n_imgs = n;
-        p->d2[l].n_strips = begin;
+        memset(&bl->d2[l], 0, sizeof(D2Args));
+        bl->d2[l].imgs = reinterpret_cast<const D2Image*>(td);
+        bl->d2[l].n_imgs = n;
+        bl->d2[l].n_strips = begin;
         th += al256(sizeof(D2Image) * n);
         td += al256(sizeof(D2Image) * n);
     }
@@ -199,26 +228,14 @@ mdn_status prepare(mdn_plan* p, const mdn_image* in, const mdn_image* out, int n
         SelImage* t = reinterpret_cast<SelImage*>(th);
         int begin = 0;
         for (int i = 0; i < n; ++i) {
-            const mdn_image& z = p->zl[(size_t)i * (L + 1) + l];
-            SelImage& d = t[i];
-            memset(&d, 0, sizeof(d));
-            d.z = z.data;
-            d.s = p->smap[i];
-            d.z_row = z.row_pitch;
-            d.z_plane = z.plane_pitch;
-            d.s_pitch = z.width;
-            d.W = z.width;
-            d.H = z.height;
-            d.C = 3;
-            d.nsx = (z.width + kSelLanesOut - 1) / kSelLanesOut;
-            d.rows = p->tuned ? p->rows_sel[l] : select_walk_rows(z.width, z.height, ncu);
-            d.strip_begin = begin;
-            begin += d.nsx * ((z.height + d.rows - 1) / d.rows);
+            t[i] = sel[(size_t)i * L + l];
+            t[i].strip_begin = begin;
+            begin += strips_of(t[i]);
         }
-        p->sel[l] = p->selc[l];
-        p->sel[l].imgs = reinterpret_cast<const SelImage*>(td);
-        p->sel[l].n_imgs = n;
-        p->sel[l].n_strips = begin;
+        bl->sel[l] = selc[l];
+        bl->sel[l].imgs = reinterpret_cast<const SelImage*>(td);
+        bl->sel[l].n_imgs = n;
+        bl->sel[l].n_strips = begin;
         th += al256(sizeof(SelImage) * n);
         td += al256(sizeof(SelImage) * n);
     }
@@ -226,57 +243,87 @@ mdn_status prepare(mdn_plan* p, const mdn_image* in, const mdn_image* out, int n
         WalkImage* t = reinterpret_cast<WalkImage*>(th);
         int begin = 0;
         for (int i = 0; i < n; ++i) {
-            const mdn_image& z = p->zl[(size_t)i * (L + 1) + l];
-            const mdn_image& uc = (l == L - 1) ? p->zl[(size_t)i * (L + 1) + L] : p->ul[(size_t)i * (L + 1) + l + 1];
-            const mdn_image& o = p->ul[(size_t)i * (L + 1) + l];
-            fill_walk_image(t[i], z, uc, o, begin);
-            t[i].s_map = p->smap[i];
-            t[i].s_pitch = z.width;
-            t[i].rows = p->tuned ? p->rows_walk[l] : walk_rows(z.width, z.height, ncu * 4);
-            begin += t[i].nsx * ((z.height + t[i].rows - 1) / t[i].rows);
+            t[i] = walk[(size_t)i * L + l];
+            t[i].strip_begin = begin;
+            begin += strips_of(t[i]);
         }
-        memset(&p->walk[l], 0, sizeof(WalkArgs));
-        p->walk[l].imgs = reinterpret_cast<const WalkImage*>(td);
-        p->walk[l].n_imgs = n;
-        p->walk[l].n_strips = begin;
-        p->walk[l].coeffs = p->lv[l].coeffs;
-        p->walk[l].coeff_dtype = p->lv[l].coeff_dtype;
-        p->walk[l].K = p->lv[l].q_theta * p->lv[l].q_s * p->lv[l].q_c;
+        memset(&bl->walk[l], 0, sizeof(WalkArgs));
+        bl->walk[l].imgs = reinterpret_cast<const WalkImage*>(td);
+        bl->walk[l].n_imgs = n;
+        bl->walk[l].n_strips = begin;
+        bl->walk[l].coeffs = lv[l].coeffs;
+        bl->walk[l].coeff_dtype = lv[l].coeff_dtype;
+        bl->walk[l].K = lv[l].q_theta * lv[l].q_s * lv[l].q_c;
         th += al256(sizeof(WalkImage) * n);
         td += al256(sizeof(WalkImage) * n);
     }
-    if (hipMemcpyAsync(p->tab_dev, p->tab_host, (size_t)(th - p->tab_host), hipMemcpyHostToDevice, p->stream) !=
-        hipSuccess)
+    bl->L = L;
+    bl->storage = storage;
+    bl->in_dtype = in[0].dtype;
+    bl->out_dtype = out[0].dtype;
+    bl->table_bytes = (size_t)(th - tab_host);
+    return MDN_OK;
+}
+
+mdn_status launch_batch_level_d2(const BatchLaunch& b, int l, hipStream_t st) {
+    return launch_down2_args(b.d2[l], 3, l == 0 ? b.in_dtype : b.storage, b.storage, st);
+}
+mdn_status launch_batch_level_sel(const BatchLaunch& b, int l, hipStream_t st) {
+    return launch_select_args(b.sel[l], 3, l == 0 ? b.in_dtype : b.storage, st);
+}
+mdn_status launch_batch_level_walk(const BatchLaunch& b, int l, hipStream_t st) {
+    return launch_walk_args(b.walk[l], l == 0 ? b.in_dtype : b.storage, b.storage, l == 0 ? b.out_dtype : b.storage, st);
+}
+
+mdn_status launch_batch(const BatchLaunch& b, hipStream_t st) {
+    mdn_status e;
+    for (int l = 0; l < b.L; ++l)
+        if ((e = launch_batch_level_d2(b, l, st))) return e;
+    for (int l = b.L - 1; l >= 0; --l) {
+        if ((e = launch_batch_level_sel(b, l, st))) return e;
+        if ((e = launch_batch_level_walk(b, l, st))) return e;
+    }
+    return MDN_OK;
+}
+
+}  // namespace mdn
+
+namespace {
+
+// Carve the per-image workspaces out of the plan's workspace and build the launch tables.
+mdn_status prepare(mdn_plan* p, const mdn_image* in, const mdn_image* out, int n) {
+    const int L = p->L;
+    size_t need = 0;
+    for (int i = 0; i < n; ++i) need += batch_image_ws(in[i].width, in[i].height, L, p->storage);
+    mdn_status st;
+    if ((st = ensure_ws(p, need))) return st;
+    if ((st = ensure_tables(p, batch_table_bytes(n, L)))) return st;
+    if (hipStreamSynchronize(p->stream) != hipSuccess) return fail(MDN_EDEVICE, "plan: sync failed");
+    std::vector<void*> ws(n);
+    char* w = p->ws;
+    for (int i = 0; i < n; ++i) {
+        ws[i] = w;
+        w += batch_image_ws(in[i].width, in[i].height, L, p->storage);
+    }
+    int rows[kMaxLevels][3];
+    for (int l = 0; l < L; ++l) {
+        rows[l][0] = p->rows_d2[l];
+        rows[l][1] = p->rows_sel[l];
+        rows[l][2] = p->rows_walk[l];
+    }
+    if ((st = build_batch(p->lv, p->selc, L, p->storage, in, out, ws.data(), n, p->tuned ? rows : nullptr,
+                          p->tab_host, p->tab_dev, &p->bl)))
+        return st;
+    if (hipMemcpyAsync(p->tab_dev, p->tab_host, p->bl.table_bytes, hipMemcpyHostToDevice, p->stream) != hipSuccess)
         return fail(MDN_EDEVICE, "plan: table upload failed");
-    p->in_dtype = in[0].dtype;
-    p->out_dtype = out[0].dtype;
     p->tables_valid = true;
     return MDN_OK;
 }
 
-mdn_status run_d2(mdn_plan* p, int l) {
-    const int ind = l == 0 ? p->in_dtype : p->storage;
-    return launch_down2_args(p->d2[l], 3, ind, p->storage, p->stream);
-}
-mdn_status run_sel(mdn_plan* p, int l) {
-    return launch_select_args(p->sel[l], 3, l == 0 ? p->in_dtype : p->storage, p->stream);
-}
-mdn_status run_walk(mdn_plan* p, int l) {
-    const int zd = l == 0 ? p->in_dtype : p->storage;
-    const int od = l == 0 ? p->out_dtype : p->storage;
-    return launch_walk_args(p->walk[l], zd, p->storage, od, p->stream);
-}
-
-mdn_status launch_all(mdn_plan* p) {
-    mdn_status st;
-    for (int l = 0; l < p->L; ++l)
-        if ((st = run_d2(p, l))) return st;
-    for (int l = p->L - 1; l >= 0; --l) {
-        if ((st = run_sel(p, l))) return st;
-        if ((st = run_walk(p, l))) return st;
-    }
-    return MDN_OK;
-}
+mdn_status run_d2(mdn_plan* p, int l) { return launch_batch_level_d2(p->bl, l, p->stream); }
+mdn_status run_sel(mdn_plan* p, int l) { return launch_batch_level_sel(p->bl, l, p->stream); }
+mdn_status run_walk(mdn_plan* p, int l) { return launch_batch_level_walk(p->bl, l, p->stream); }
+mdn_status launch_all(mdn_plan* p) { return launch_batch(p->bl, p->stream); }
 
 void drop_graph(mdn_plan* p) {
     if (p->exec) hipGraphExecDestroy(p->exec);
@@ -398,9 +445,8 @@ mdn_status mdn_plan_autotune(mdn_plan* p, const mdn_image* in, const mdn_image* 
     // every candidate re-prepares the tables of that kernel and level only through `tuned` rows
     const int c_d2[] = {8, 16, 32, 64}, c_sel[] = {10, 20, 30, 60}, c_walk[] = {14, 28, 42, 56};
     int best_d2[kMaxLevels], best_sel[kMaxLevels], best_walk[kMaxLevels];
-    const int ncu = device_cus();
     for (int l = 0; l < L; ++l) {
-        best_d2[l] = down2_rows(p->zl[l + 1].width, p->zl[l + 1].height, ncu);
+        best_d2[l] = 32;
         best_sel[l] = 20;
         best_walk[l] = 56;
     }

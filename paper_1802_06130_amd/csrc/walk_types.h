@@ -83,4 +83,31 @@ mdn_status launch_walk_args(const WalkArgs& a, int z_dtype, int uc_dtype, int o_
 mdn_status launch_select_args(const SelWalkArgs& a, int channels, int z_dtype, hipStream_t st);
 mdn_status launch_down2_args(const D2Args& a, int channels, int in_dtype, int out_dtype, hipStream_t st);
 
+
+// ---------------------------------------------------------------- batched cascade
+constexpr int kMaxLevels = 8;
+
+struct BatchLaunch {
+    int L, storage, in_dtype, out_dtype;
+    size_t table_bytes;
+    D2Args d2[kMaxLevels];
+    SelWalkArgs sel[kMaxLevels];
+    WalkArgs walk[kMaxLevels];
+};
+
+size_t batch_image_ws(int w, int h, int L, int storage);
+size_t batch_table_bytes(int n, int L);
+void describe_cascade(const mdn_image& in, const mdn_image& out, void* ws, int L, int storage, const int (*rows)[3],
+                      int ncu, D2Image* d2, SelImage* sel, WalkImage* walk);
+int strips_of(const D2Image& d);
+int strips_of(const SelImage& d);
+int strips_of(const WalkImage& d);
+mdn_status build_batch(const mdn_level* lv, const SelWalkArgs* selc, int L, int storage, const mdn_image* in,
+                       const mdn_image* out, void* const* ws, int n, const int (*rows)[3], char* tab_host,
+                       char* tab_dev, BatchLaunch* bl);
+mdn_status launch_batch_level_d2(const BatchLaunch& b, int l, hipStream_t st);
+mdn_status launch_batch_level_sel(const BatchLaunch& b, int l, hipStream_t st);
+mdn_status launch_batch_level_walk(const BatchLaunch& b, int l, hipStream_t st);
+mdn_status launch_batch(const BatchLaunch& b, hipStream_t st);
+
 }  // namespace mdn
