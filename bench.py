@@ -211,6 +211,70 @@ def run_served(M, torch, banks16, rates, n_requests):
     return report
 
 
+TRAIN_PAIRS, TRAIN_SIZE = 256, 512
+FP32_MFMA_PEAK_TFLOPS = 157.3
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+
+
+def _make_train_pair(args):
+    seed, sigma = args
+    z, u = synth.noisy_pair(seed, TRAIN_SIZE, TRAIN_SIZE, 3, sigma)
+    return z, u
+
+
+def run_training(M, torch):
+    """Training throughput on 256 seeded 512x512 RGB pairs (sigma per pair from {15, 25, 50}/255,
+    rng(3)), 3-level pyramid: accumulation of the level-0 normal equations (D = 98 per channel, 67.1 M
+    samples) in both Gram precisions, then the level's FP64 solve (648 systems)."""
+    rng = np.random.default_rng(3)
+    sig = rng.choice([15.0, 25.0, 50.0], TRAIN_PAIRS)
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    with mp.get_context("fork").Pool(workers) as pool:
+        pairs = pool.map(_make_train_pair, [(1 + i, float(g)) for i, g in enumerate(sig)], chunksize=8)
+    dev = torch.device("cuda:0")
+    zs = [torch.from_numpy(z).to(dev) for z, _ in pairs]
+    us = [torch.from_numpy(u).to(dev) for _, u in pairs]
+    del pairs
+    coarse = [M.pyramid_build(z, 1)[0] for z in zs]
+    t_s, t_c = M.level_thresholds(zs[:32], Q_S, Q_C)
+    K, C, D = Q_THETA * Q_S * Q_C, 3, 98
+    sel = M.Level(Q_THETA, t_s, t_c, RADIUS, RADIUS, torch.zeros((K, C, D), device=dev), 3)
+    stream = torch.cuda.current_stream()
+    samples = TRAIN_PAIRS * TRAIN_SIZE * TRAIN_SIZE
+    useful = 2.0 * (D * D + D) * C * samples          # G and b products per sample and channel
+    issued = 2.0 * 128 * 128 * C * samples             # MFMA tiles cover D padded to 128
+    out = {"workload": f"{TRAIN_PAIRS} RGB pairs {TRAIN_SIZE}x{TRAIN_SIZE}, level 0 of a 3-level pyramid, "
+                       f"D = 98 per channel, {K} buckets, {samples / 1e6:.1f} M samples"}
+    g = None
+    for name, prec, peak, mult in (("fp32_mfma", M.GRAM_F32, FP32_MFMA_PEAK_TFLOPS, 1),
+                                   ("bf16x3_mfma", M.GRAM_BF16X3, BF16_MFMA_PEAK_TFLOPS, 3)):
+        g = M.Gram(K, C, RADIUS, RADIUS, device=dev)
+        ws = M.train_accumulate(g, zs[0], us[0], sel, u_coarse=coarse[0], coarse_color=M.RGB, precision=prec)
+        g.zero()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for z, u, c in zip(zs, us, coarse):
+            M.train_accumulate(g, z, u, sel, u_coarse=c, coarse_color=M.RGB, precision=prec, ws=ws)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) * 1e-3
+        out[name] = {"accumulate_ms": round(sec * 1e3, 2), "samples_per_s": round(samples / sec / 1e9, 3),
+                     "samples_unit": "G/s", "useful_TFLOPs": round(useful / sec / 1e12, 2),
+                     "mfma_issued_TFLOPs": round(issued * mult / sec / 1e12, 2),
+                     "mfma_frac": round(issued * mult / sec / 1e12 / peak, 4), "peak_TFLOPs": peak}
+        print(f"# training {name}: {out[name]}", file=sys.stderr, flush=True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    co, nfb = M.train_solve(g, 1e-3)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    out["solve_ms"] = round(e0.elapsed_time(e1), 3)
+    out["solve_systems"] = K * C
+    out["fallback_systems"] = nfb
+    return out
+
+
 def time_level0_filter(M, torch, zs, bank, n=16, reps=3):
     """The dominant kernel, the level-0 filtering pass, timed alone with HIP events on its stream
     (the selector map and the coarser output are prepared first)."""
@@ -315,6 +379,7 @@ def main():
     ap.add_argument("--no-f32", action="store_true")
     ap.add_argument("--pmc-probe", action="store_true", help="run only the hardware-counter probe")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-train", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2000)
     args = ap.parse_args()
     if args.pmc_probe:
@@ -406,6 +471,8 @@ def main():
     }
     if f32 is not None:
         line["plain_f32"] = f32
+    if not args.no_train:
+        line["training"] = run_training(M, torch)
     if not args.no_serve:
         del zs
         torch.cuda.empty_cache()

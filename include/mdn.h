@@ -176,8 +176,9 @@ mdn_status mdn_gram_dims(const mdn_gram* g, int32_t* D, int32_t* nrhs, int32_t* 
 /* Zero the accumulators (enqueued on stream). */
 mdn_status mdn_gram_zero(const mdn_gram* g, void* stream);
 
-/* Bytes of workspace mdn_train_accumulate needs for a width x height level. */
-mdn_status mdn_train_workspace_size(int32_t width, int32_t height, int32_t channels, size_t* bytes);
+/* Bytes of workspace mdn_train_accumulate needs for this gram and a width x height level
+ * (float32 planes, the selector map, the bucket sort and the per-segment partial tiles). */
+mdn_status mdn_train_workspace_size(const mdn_gram* g, int32_t width, int32_t height, size_t* bytes);
 
 /* Add one training pair's samples at one level to the normal equations (Eq. (8)):
  * z:        noisy level z^l (RGB or grey); selects s(i) with `sel` (thresholds; coefficients unused);

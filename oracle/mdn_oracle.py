@@ -32,6 +32,7 @@ __all__ = [
     "LevelBank", "Bank", "apply_level", "denoise",
     "thresholds_from_features", "level_features", "GramStats", "patch_matrix",
     "accumulate_level", "solve_level", "train_single", "train_multiscale",
+    "CrossGramStats", "accumulate_level_cross", "solve_level_cross", "apply_level_cross",
     "psnr", "round_storage",
 ]
 
@@ -489,6 +490,83 @@ def solve_level(stats: GramStats, lam: float, n_min: Optional[int] = None):
                 nk = stats.n[k]
                 out[k, ch] = np.linalg.solve(stats.G[k, ch] / nk + lam * eye, stats.b[k, ch] / nk)
     return out, fallback
+
+
+# --------------------------------------------------------------------------------------
+# Cross-channel regression (a reading of a literal 147-tap feature vector: the 7x7 patches of
+# all three filter-space channels concatenated, one system per bucket with one right-hand side
+# per output channel). Not used by the paper's per-channel inference; kept for the training
+# precision study.
+
+@dataclass
+class CrossGramStats:
+    """Per bucket k: G = sum x x^T (one matrix), b[c] = sum x y_c, yy[c] = sum y_c^2; n = count."""
+    G: np.ndarray   # (K, D, D), D = C * taps
+    b: np.ndarray   # (K, C, D)
+    n: np.ndarray   # (K,)
+    yy: np.ndarray  # (K, C)
+
+    @staticmethod
+    def zeros(K: int, C: int, D: int) -> "CrossGramStats":
+        return CrossGramStats(np.zeros((K, D, D)), np.zeros((K, C, D)), np.zeros(K, dtype=np.int64),
+                              np.zeros((K, C)))
+
+
+def _cross_patches(z_f: np.ndarray, radius: int) -> np.ndarray:
+    return np.concatenate([patch_matrix(z_f[ch], radius) for ch in range(z_f.shape[0])], axis=1)
+
+
+def accumulate_level_cross(stats: CrossGramStats, s: np.ndarray, z_f: np.ndarray, target_f: np.ndarray,
+                           radius: int):
+    """x_i = [R_i z_0; R_i z_1; ...; R_i z_{C-1}], y_i = target at i (all channels), k = s(i)."""
+    C = z_f.shape[0]
+    sk = np.asarray(s).ravel()
+    K = stats.G.shape[0]
+    stats.n += np.bincount(sk, minlength=K)
+    X = _cross_patches(z_f, radius)
+    Y = np.asarray(target_f, dtype=np.float64).reshape(C, -1)
+    for k in np.unique(sk):
+        sel = sk == k
+        Xk = X[sel]
+        stats.G[k] += Xk.T @ Xk
+        for ch in range(C):
+            yk = Y[ch, sel]
+            stats.b[k, ch] += Xk.T @ yk
+            stats.yy[k, ch] += yk @ yk
+    return stats
+
+
+def solve_level_cross(stats: CrossGramStats, lam: float, n_min: Optional[int] = None):
+    """h_{k,c} = (G_k / n_k + lam I)^{-1} b_{k,c} / n_k, pooled solution for sparse buckets.
+
+    Returns (coeffs (K, C, D), fallback mask (K,))."""
+    K, C, D = stats.b.shape
+    if n_min is None:
+        n_min = D
+    eye = np.eye(D)
+    n_all = stats.n.sum()
+    fallback = stats.n < n_min
+    out = np.zeros((K, C, D))
+    Gp, bp = stats.G.sum(axis=0), stats.b.sum(axis=0)
+    for ch in range(C):
+        pooled = np.linalg.solve(Gp / max(n_all, 1) + lam * eye, bp[ch] / max(n_all, 1)) if n_all > 0 else np.zeros(D)
+        for k in range(K):
+            if fallback[k]:
+                out[k, ch] = pooled
+            else:
+                out[k, ch] = np.linalg.solve(stats.G[k] / stats.n[k] + lam * eye, stats.b[k, ch] / stats.n[k])
+    return out, fallback
+
+
+def apply_level_cross(z_f: np.ndarray, s: np.ndarray, coeffs: np.ndarray, radius: int) -> np.ndarray:
+    """Output channel c at i: sum over input channels c' and taps j of h[s(i)][c][c' taps + j] z_{c'}(i+j)."""
+    C, H, W = z_f.shape
+    X = _cross_patches(z_f, radius)
+    sk = np.asarray(s).ravel()
+    out = np.empty((C, H * W))
+    for ch in range(C):
+        out[ch] = np.einsum("nd,nd->n", X, coeffs[sk, ch])
+    return out.reshape(C, H, W)
 
 
 def train_single(pairs, q_theta: int, q_s: int, q_c: int, radius: int, lam: float,

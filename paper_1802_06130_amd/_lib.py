@@ -248,7 +248,7 @@ def _train_sigs(L):
     sig = {
         "mdn_gram_dims": [P(MdnGram), P(i32), P(i32), P(i32)],
         "mdn_gram_zero": [P(MdnGram), vp],
-        "mdn_train_workspace_size": [i32, i32, i32, P(ct.c_size_t)],
+        "mdn_train_workspace_size": [P(MdnGram), i32, i32, P(ct.c_size_t)],
         "mdn_train_accumulate": [P(MdnGram), P(MdnImage), P(MdnImage), P(MdnImage), P(MdnLevel), i32, vp,
                                  ct.c_size_t, vp],
         "mdn_train_solve_workspace_size": [P(MdnGram), P(ct.c_size_t)],
@@ -298,7 +298,7 @@ def train_accumulate(gram: Gram, z, target, level: Level, u_coarse=None, precisi
     C, H, W = z.shape
     _train_sigs(lib())
     need = ct.c_size_t()
-    _check(lib().mdn_train_workspace_size(W, H, C, ct.byref(need)))
+    _check(lib().mdn_train_workspace_size(ct.byref(gram.desc()), W, H, ct.byref(need)))
     if ws is None or ws.numel() < need.value:
         ws = _ws(need.value, z.device)
     uc = None

@@ -306,12 +306,13 @@ mdn_status mdn_gram_zero(const mdn_gram* g, void* stream) {
     return gram_zero(*g, static_cast<hipStream_t>(stream));
 }
 
-mdn_status mdn_train_workspace_size(int32_t width, int32_t height, int32_t channels, size_t* bytes) {
+mdn_status mdn_train_workspace_size(const mdn_gram* g, int32_t width, int32_t height, size_t* bytes) {
     g_err[0] = 0;
     if (!bytes) return fail(MDN_EINVAL, "null bytes");
+    mdn_status st = check_gram(g);
+    if (st) return st;
     if (width < 0 || height < 0) return fail(MDN_EINVAL, "negative size");
-    if (channels != 1 && channels != 3) return fail(MDN_EINVAL, "channels must be 1 or 3");
-    *bytes = train_ws_bytes(width, height, channels);
+    *bytes = train_ws_bytes(*g, width, height);
     return MDN_OK;
 }
 
@@ -340,8 +341,14 @@ mdn_status mdn_train_accumulate(const mdn_gram* g, const mdn_image* z, const mdn
         return fail(MDN_EINVAL, "u_coarse given for a layout without upscale block");
     }
     if (empty(*z)) return MDN_OK;
-    if (!ws || ws_bytes < train_ws_bytes(z->width, z->height, z->channels))
-        return fail(MDN_ENOMEM, "workspace too small (need %zu)", train_ws_bytes(z->width, z->height, z->channels));
+    {
+        // the sample gathers address the float32 planes with 32-bit element offsets
+        const int64_t px = (int64_t)z->width * z->height;
+        const int64_t elems = 2 * px * z->channels + (int64_t)half_up(z->width) * half_up(z->height) * z->channels + 256;
+        if (elems > 0x7fffffffLL) return fail(MDN_ENOTSUP, "train_accumulate: image too large (2^31 elements)");
+    }
+    if (!ws || ws_bytes < train_ws_bytes(*g, z->width, z->height))
+        return fail(MDN_ENOMEM, "workspace too small (need %zu)", train_ws_bytes(*g, z->width, z->height));
     if (((uintptr_t)ws) & 255) return fail(MDN_EINVAL, "workspace must be 256-byte aligned");
     return train_accumulate(*g, *z, g->radius_f >= 1 ? u_coarse : nullptr, *target, *sel, precision, ws,
                             static_cast<hipStream_t>(stream));

@@ -100,7 +100,7 @@ mdn_status launch_features(const mdn_image& z, double* strength, double* coheren
 // training
 int gram_dims(const mdn_gram& g, int* D, int* nrhs, int* sys_per_k);
 mdn_status gram_zero(const mdn_gram& g, hipStream_t st);
-size_t train_ws_bytes(int w, int h, int C);
+size_t train_ws_bytes(const mdn_gram& g, int w, int h);
 mdn_status train_accumulate(const mdn_gram& g, const mdn_image& z, const mdn_image* uc, const mdn_image& target,
                             const mdn_level& sel, int precision, void* ws, hipStream_t st);
 size_t solve_ws_bytes(const mdn_gram& g);

@@ -4,21 +4,29 @@
 // which is one linear regression per bucket (and per YCbCr channel, footnote of Section 3).
 // The normal equations are accumulated here and solved with a ridge term.
 //
-// Accumulation (k_gram): one workgroup per (bucket, system). It walks the selector map in
-// raster order, compacts the matching pixel indices with a block-wide scan (a fixed order, so
-// the sums are bitwise reproducible), gathers 64 samples at a time into LDS as a feature-major
-// matrix X^T (regression taps followed by the target value(s), zero padded to a multiple of 32),
+// Grouping: the pixel indices of the level are sorted by bucket with a stable radix sort of the
+// selector map (8-bit keys), so every bucket's pixels form one contiguous run in raster order,
+// and the run boundaries come from a binary search per bucket.
+//
+// Accumulation (k_gram): one workgroup per (bucket, system, segment). A bucket's run is cut into
+// up to kMaxSeg equal segments of whole 64-sample chunks, so that large buckets do not leave the
+// rest of the device idle. A workgroup gathers 64 samples at a time into LDS as a feature-major
+// matrix X^T (regression taps followed by the target value(s), zero padded to a multiple of 32;
+// the gathers of the next chunk are in flight while the current one is multiplied),
 // and accumulates the upper-triangle 32x32 tiles of X^T X on MFMA with FP32 accumulators. The
 // target value rides along as an extra feature, so the same tiles yield G = sum x x^T,
 // b = sum x y and yy = sum y^2. Two products are offered:
 //   MDN_GRAM_F32    : v_mfma_f32_32x32x2_f32 - exact FP32 products, FP32 accumulation;
 //   MDN_GRAM_BF16X3 : v_mfma_f32_32x32x16_bf16 on a hi/lo split x = hi + lo (hi = bf16(x),
 //                     lo = bf16(x - hi)); x y ~ hi_x hi_y + hi_x lo_y + lo_x hi_y.
-// Each workgroup adds its FP32 tiles once into the FP64 accumulators of its system.
+// Each workgroup writes its FP32 tiles to a partial buffer; k_gram_reduce then adds the segments
+// of each system in segment order into the FP64 accumulators (fixed order: bitwise reproducible).
 //
 // Solve (k_solve): one workgroup per system, (G/n + lambda I) h = b/n by Cholesky in float64,
 // the lower triangle packed in LDS. Buckets with fewer than min_count samples (or a failed
 // factorisation) take the pooled solution of the level (sums over all buckets).
+
+#include <hipcub/hipcub.hpp>
 
 #include "mdn_internal.h"
 
@@ -34,9 +42,23 @@ typedef float f16v __attribute__((ext_vector_type(16)));
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 
 constexpr int kChunk = 64;                 // samples per MFMA chunk
-constexpr int kLdw = kChunk + 8;           // LDS row stride (elements) of X^T
-constexpr int kScan = 1024;                // pixels examined per scan step (4 per thread)
-constexpr int kListCap = kChunk + kScan;   // pending sample list capacity
+constexpr int kMaxSeg = 16;                // segments per bucket run
+constexpr int kMinSegChunks = 8;           // chunks per segment, at least
+
+// chunks per segment of a run of `chunks` chunks (segments after the run's end stay idle)
+__host__ __device__ inline int seg_chunks(int chunks, int nseg) {
+    const int per = (chunks + nseg - 1) / nseg;
+    return per > kMinSegChunks ? per : kMinSegChunks;
+}
+// LDS row stride (elements) of X^T: bf16 rows keep 16-byte aligned 8-element reads; f32 rows
+// use a stride of 2 mod 64 dwords so that the 64 lanes of an MFMA operand read (32 rows x 2
+// columns) fall in 64 distinct banks.
+template <int PREC> struct Ldw { static constexpr int v = PREC == 0 ? kChunk + 2 : kChunk + 8; };
+
+int gram_segments(int64_t npx) {
+    const int64_t s = (npx + 16383) / 16384;
+    return (int)(s < 1 ? 1 : (s > kMaxSeg ? kMaxSeg : s));
+}
 
 // feature descriptor: source (0 fine, 1 coarse, 2 target), plane, dy, dx
 __host__ __device__ inline int feat_pack(int src, int plane, int dy, int dx) {
@@ -44,15 +66,18 @@ __host__ __device__ inline int feat_pack(int src, int plane, int dy, int dx) {
 }
 
 struct GramArgs {
-    const float* fine;      // YCbCr (or grey) planes of z^l, float32
-    const float* coarse;    // planes of the coarser output u^{l+1}, float32 (may be null)
-    const float* target;    // planes of the clean level u^l, float32
-    int64_t f_row, f_plane, c_row, c_plane;
+    // YCbCr (or grey) planes of z^l, of the clean level u^l and of the coarser output u^{l+1},
+    // float32, in one buffer: target and coarse planes start at the given element offsets
+    const float* planes;
+    int32_t target_off, coarse_off;
+    int32_t f_row, f_plane, c_row, c_plane;
     int32_t W, H, Wc, Hc;
-    const uint8_t* s;
-    int64_t s_pitch;
+    const int32_t* idx;     // pixel indices sorted by bucket (raster order within a bucket)
+    const int32_t* off;     // [K+1] start of each bucket's run in idx
     int32_t D, Daug, nrhs, per_channel;
+    int32_t nseg;           // segments per bucket run
     int32_t feat[kMaxFeat];
+    float* part;            // [K][systems per bucket][nseg][tiles][1024] partial tiles
     double* G;
     double* b;
     int64_t* n;
@@ -70,55 +95,57 @@ __device__ __forceinline__ float from_bf16(__bf16 h) {
     return __uint_as_float((uint32_t)__builtin_bit_cast(unsigned short, h) << 16);
 }
 
-// Block-wide exclusive scan of one int per thread (256 threads). Returns the prefix; *total
-// receives the block sum. Contains barriers: call from uniform control flow.
-__device__ int block_scan(int v, int* buf, int* total) {
-    const int t = threadIdx.x;
-    buf[t] = v;
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-        const int add = t >= off ? buf[t - off] : 0;
-        __syncthreads();
-        buf[t] += add;
-        __syncthreads();
+// Tile t of the upper triangle (P <= Q, row-major over P) -> (P, Q).
+__host__ __device__ inline void tile_pq(int T, int t, int* P, int* Q) {
+    int p = 0;
+    while (t >= T - p) {
+        t -= T - p;
+        ++p;
     }
-    const int incl = buf[t];
-    *total = buf[255];
-    __syncthreads();
-    return incl - v;
+    *P = p;
+    *Q = p + t;
 }
 
 template <int PREC, int T>
-__global__ __launch_bounds__(256) void k_gram(GramArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_gram(GramArgs a) {
     constexpr int DPAD = 32 * T;
     constexpr int NT = T * (T + 1) / 2;
     constexpr int TPW = (NT + 3) / 4;
+    constexpr int LDW = Ldw<PREC>::v;
     using XT = typename std::conditional<PREC == 0, float, __bf16>::type;
-    __shared__ XT xhi[DPAD][kLdw];
-    __shared__ XT xlo[PREC == 0 ? 1 : DPAD][PREC == 0 ? 1 : kLdw];
-    __shared__ int plist[kListCap];
-    __shared__ int sbuf[256];
+    __shared__ XT xhi[DPAD][LDW];
+    __shared__ XT xlo[PREC == 0 ? 1 : DPAD][PREC == 0 ? 1 : LDW];
+    __shared__ int feat[kMaxFeat];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int k = blockIdx.x;
     const int sys_c = blockIdx.y;                      // channel (per-channel systems) or 0
+    const int seg = blockIdx.z;
     const int plane_off = a.per_channel ? sys_c : 0;
     const int W = a.W, H = a.H;
-    const int64_t N = (int64_t)W * H;
 
-    // tiles owned by this wave
+    // this segment's chunks of the bucket's run
+    const int beg = a.off[k], end = a.off[k + 1];
+    const int chunks = (end - beg + kChunk - 1) / kChunk;
+    const int per = seg_chunks(chunks, a.nseg);
+    const int c0 = seg * per, c1 = min(chunks, c0 + per);
+    if (c0 >= c1) return;
+
+    // launch constants as wave-uniform values (selected arithmetically in the gather)
+    const float* planes = a.planes;
+    const int target_off = __builtin_amdgcn_readfirstlane(a.target_off);
+    const int coarse_off = __builtin_amdgcn_readfirstlane(a.coarse_off);
+    const int f_row = __builtin_amdgcn_readfirstlane(a.f_row), f_plane = __builtin_amdgcn_readfirstlane(a.f_plane);
+    const int c_row = __builtin_amdgcn_readfirstlane(a.c_row), c_plane = __builtin_amdgcn_readfirstlane(a.c_plane);
+    const int h1 = H - 1, w1 = W - 1;
+    const int hc1 = __builtin_amdgcn_readfirstlane(a.Hc - 1), wc1 = __builtin_amdgcn_readfirstlane(a.Wc - 1);
+    const int daug = __builtin_amdgcn_readfirstlane(a.Daug);
+    for (int f = tid; f < kMaxFeat; f += 256) feat[f] = f < daug ? a.feat[f] : 0;
+
+    // tiles owned by this wave: t = wave, wave + 4, ...
     int tP[TPW], tQ[TPW];
-    {
-        int t = 0;
-        for (int P = 0; P < T; ++P)
-            for (int Q = P; Q < T; ++Q) {
-                if (t % 4 == wave && t / 4 < TPW) {
-                    tP[t / 4] = P;
-                    tQ[t / 4] = Q;
-                }
-                ++t;
-            }
-    }
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) tile_pq(T, min(wave + 4 * i, NT - 1), &tP[i], &tQ[i]);
     const int my_tiles = (NT - wave + 3) / 4;
     f16v acc[TPW];
 #pragma unroll
@@ -126,42 +153,60 @@ __global__ __launch_bounds__(256) void k_gram(GramArgs a) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[i][r] = 0.0f;
 
-    auto process = [&](int count) {
-        // gather X^T for `count` samples (the rest of the chunk is zero)
-        for (int i = tid; i < DPAD * kChunk; i += 256) {
-            const int f = i / kChunk, p = i - f * kChunk;
-            float v = 0.0f;
-            if (p < count && f < a.Daug) {
-                const int pix = plist[p];
-                const int y = pix / W, x = pix - y * W;
-                const int e = a.feat[f];
-                const int src = e >> 24, pl = ((e >> 16) & 0xff) + plane_off;
-                const int dy = ((e >> 8) & 0xff) - 128, dx = (e & 0xff) - 128;
-                if (src == 0) {
-                    v = a.fine[pl * a.f_plane + (int64_t)clampi(y + dy, 0, H - 1) * a.f_row + clampi(x + dx, 0, W - 1)];
-                } else if (src == 1) {
-                    v = a.coarse[pl * a.c_plane + (int64_t)clampi(y / 2 + dy, 0, a.Hc - 1) * a.c_row +
-                                 clampi(x / 2 + dx, 0, a.Wc - 1)];
-                } else {
-                    v = a.target[pl * a.f_plane + (int64_t)y * a.f_row + x];
-                }
-            }
+    // Gather: four threads share a sample and take every fourth feature. All loads of a chunk
+    // are issued at once (branch-free addressing from one base pointer; lanes without a sample
+    // or feature read element 0) and consumed only when the chunk is stored to LDS.
+    constexpr int kPer = DPAD / 4;
+    static_assert(kPer <= 64, "sample mask holds 64 features per thread");
+    const int sp = tid >> 2, sq = tid & 3;
+    float v[kPer];
+    uint64_t okm = 0;
+    auto load = [&](int chunk) {
+        const int base = beg + chunk * kChunk;
+        const bool live = base + sp < end;
+        const int pix = live ? a.idx[base + sp] : 0;
+        const int y = pix / W, x = pix - (pix / W) * W;
+        okm = 0;
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int f = sq + 4 * j;
+            const bool ok = live && f < daug;
+            const int e = feat[f < kMaxFeat ? f : 0];
+            const int src = e >> 24, pl = ((e >> 16) & 0xff) + plane_off;
+            const int dy = ((e >> 8) & 0xff) - 128, dx = (e & 0xff) - 128;
+            const bool cs = src == 1;
+            const int yb = cs ? (y >> 1) : y, xb = cs ? (x >> 1) : x;
+            const int hm = cs ? hc1 : h1, wm = cs ? wc1 : w1;
+            const int row = cs ? c_row : f_row, pls = cs ? c_plane : f_plane;
+            const int start = src == 0 ? 0 : (cs ? coarse_off : target_off);
+            const int o = start + pl * pls + clampi(yb + dy, 0, hm) * row + clampi(xb + dx, 0, wm);
+            v[j] = planes[ok ? o : 0];
+            okm |= (uint64_t)ok << j;
+        }
+        __builtin_amdgcn_sched_barrier(0);   // keep every load ahead of the first use
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int f = sq + 4 * j;
+            const float w = (okm >> j) & 1ull ? v[j] : 0.0f;
             if constexpr (PREC == 0) {
-                xhi[f][p] = v;
+                xhi[f][sp] = w;
             } else {
-                const __bf16 h = to_bf16(v);
-                xhi[f][p] = h;
-                xlo[f][p] = to_bf16(v - from_bf16(h));
+                const __bf16 h = to_bf16(w);
+                xhi[f][sp] = h;
+                xlo[f][sp] = to_bf16(w - from_bf16(h));
             }
         }
-        __syncthreads();
+    };
+    auto multiply = [&]() {
 #pragma unroll
         for (int i = 0; i < TPW; ++i) {
             if (i < my_tiles) {
                 const int rowA = tP[i] * 32 + (lane & 31);
                 const int rowB = tQ[i] * 32 + (lane & 31);
                 if constexpr (PREC == 0) {
-#pragma unroll 4
+#pragma unroll 8
                     for (int ks = 0; ks < kChunk / 2; ++ks) {
                         const float av = xhi[rowA][2 * ks + (lane >> 5)];
                         const float bv = xhi[rowB][2 * ks + (lane >> 5)];
@@ -182,81 +227,77 @@ __global__ __launch_bounds__(256) void k_gram(GramArgs a) {
                 }
             }
         }
-        __syncthreads();
     };
 
-    int pending = 0;
-    int64_t n_total = 0;
-    for (int64_t base = 0; base < N; base += kScan) {
-        int flags = 0, cnt = 0;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int64_t p = base + 4 * tid + j;
-            if (p < N) {
-                const int y = (int)(p / W), x = (int)(p - (int64_t)y * W);
-                if (a.s[(int64_t)y * a.s_pitch + x] == k) {
-                    flags |= 1 << j;
-                    ++cnt;
-                }
-            }
-        }
-        int total;
-        const int pos = block_scan(cnt, sbuf, &total);
-        int w = pending + pos;
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-            if (flags & (1 << j)) plist[w++] = (int)(base + 4 * tid + j);
-        __syncthreads();
-        pending += total;
-        n_total += total;
-        while (pending >= kChunk) {
-            process(kChunk);
-            const int rest = pending - kChunk;
-            int moved[5];
-#pragma unroll
-            for (int j = 0; j < 5; ++j) {
-                const int i = tid + 256 * j;
-                moved[j] = i < rest ? plist[kChunk + i] : 0;
-            }
+    __syncthreads();                 // feature table
+    load(c0);
+    store();
+    __syncthreads();
+    for (int c = c0; c < c1; ++c) {
+        const bool more = c + 1 < c1;
+        if (more) load(c + 1);       // in flight during the products
+        multiply();
+        __syncthreads();             // every wave is done with this chunk
+        if (more) {
+            store();
             __syncthreads();
-#pragma unroll
-            for (int j = 0; j < 5; ++j) {
-                const int i = tid + 256 * j;
-                if (i < rest) plist[i] = moved[j];
-            }
-            __syncthreads();
-            pending = rest;
         }
     }
-    if (pending > 0) process(pending);
 
-    // add the tiles to the float64 accumulators of this system
+    // partial tiles of this segment: [system][seg][tile][r][lane]
     const int sys = a.per_channel ? k * (int)gridDim.y + sys_c : k;
+    float* part = a.part + ((int64_t)sys * a.nseg + seg) * NT * 1024;
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+        if (i >= my_tiles) continue;
+        const int t = wave + 4 * i;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) part[t * 1024 + r * 64 + lane] = acc[i][r];
+    }
+}
+
+// Sum the segment partials of each system in segment order (float64) and add them to the
+// accumulators; the result does not depend on timing.
+__global__ __launch_bounds__(256) void k_gram_reduce(GramArgs a, int T) {
+    const int NT = T * (T + 1) / 2;
+    const int k = blockIdx.x, sys_c = blockIdx.y;
+    const int sys = a.per_channel ? k * (int)gridDim.y + sys_c : k;
+    const int beg = a.off[k], end = a.off[k + 1];
+    const int chunks = (end - beg + kChunk - 1) / kChunk;
+    const int per = seg_chunks(chunks, a.nseg);
+    const int nseg = (chunks + per - 1) / per;                      // segments that ran
+    if (sys_c == 0 && threadIdx.x == 0) a.n[k] += end - beg;
+    const float* part = a.part + (int64_t)sys * a.nseg * NT * 1024;
     const int D = a.D;
     double* G = a.G + (int64_t)sys * D * D;
     double* bvec = a.b + (int64_t)sys * a.nrhs * D;
     double* yy = a.yy + (int64_t)sys * a.nrhs;
+    if (nseg == 0) return;
+    for (int e = threadIdx.x; e < NT * 1024; e += 256) {
+        // every segment's partial is loaded at once (idle segments re-read segment 0), then
+        // summed in segment order
+        float pv[kMaxSeg];
 #pragma unroll
-    for (int i = 0; i < TPW; ++i) {
-        if (i >= my_tiles) continue;
-        const int P = tP[i], Q = tQ[i];
+        for (int sg = 0; sg < kMaxSeg; ++sg) pv[sg] = part[(int64_t)(sg < nseg ? sg : 0) * NT * 1024 + e];
+        double v = 0.0;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int p = P * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-            const int q = Q * 32 + (lane & 31);
-            const double v = (double)acc[i][r];
-            if (p >= a.Daug || q >= a.Daug) continue;
-            if (p < D && q < D) {
-                G[(int64_t)p * D + q] += v;
-                if (P != Q) G[(int64_t)q * D + p] += v;
-            } else if (p < D && q >= D) {
-                bvec[(int64_t)(q - D) * D + p] += v;
-            } else if (p >= D && q >= D && p == q) {
-                yy[p - D] += v;
-            }
+        for (int sg = 0; sg < kMaxSeg; ++sg)
+            if (sg < nseg) v += (double)pv[sg];
+        const int t = e >> 10, r = (e >> 6) & 15, lane = e & 63;
+        int P, Q;
+        tile_pq(T, t, &P, &Q);
+        const int p = P * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int q = Q * 32 + (lane & 31);
+        if (p >= a.Daug || q >= a.Daug) continue;
+        if (p < D && q < D) {
+            G[(int64_t)p * D + q] += v;
+            if (P != Q) G[(int64_t)q * D + p] += v;
+        } else if (p < D && q >= D) {
+            bvec[(int64_t)(q - D) * D + p] += v;
+        } else if (p >= D && q >= D && p == q) {
+            yy[p - D] += v;
         }
     }
-    if (sys_c == 0 && tid == 0) a.n[k] += n_total;
 }
 
 // float32 YCbCr (or grey) planes of an RGB / grey image, for the sample gathers.
@@ -273,6 +314,24 @@ __global__ void k_to_planes(ImageArg in, int32_t dtype, int32_t rgb_to_ycc, int3
     }
     if (C == 3 && rgb_to_ycc) Ycc::from_rgb(v[0], v[1], v[2], v[0], v[1], v[2]);
     for (int c = 0; c < C; ++c) out[c * o_plane + (int64_t)y * o_row + x] = v[c];
+}
+
+__global__ void k_iota(int32_t* p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = (int32_t)i;
+}
+
+// off[k] = first position of a key >= k in the sorted keys, k = 0..K
+__global__ void k_bucket_bounds(const uint8_t* keys, int64_t n, int K, int32_t* off) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k > K) return;
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int)keys[mid] < k) lo = mid + 1;
+        else hi = mid;
+    }
+    off[k] = (int32_t)lo;
 }
 
 __global__ void k_fill_zero(double* p, int64_t n) {
@@ -468,10 +527,30 @@ mdn_status gram_zero(const mdn_gram& g, hipStream_t st) {
     return check_launch("gram_zero");
 }
 
-size_t train_ws_bytes(int w, int h, int C) {
+static size_t sort_tmp_bytes(int64_t n) {
+    size_t tmp = 0;
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, (const uint8_t*)nullptr, (uint8_t*)nullptr,
+                                             (const int32_t*)nullptr, (int32_t*)nullptr, (int)n, 0, 8);
+    return tmp;
+}
+
+static int gram_tiles(const mdn_gram& g) {
+    int D, nrhs, spk;
+    gram_dims(g, &D, &nrhs, &spk);
+    const int T = (D + nrhs + 31) / 32;
+    return T * (T + 1) / 2;
+}
+
+size_t train_ws_bytes(const mdn_gram& g, int w, int h) {
     auto al = [](size_t v) { return (v + 255) / 256 * 256; };
+    int D, nrhs, spk;
+    gram_dims(g, &D, &nrhs, &spk);
+    const int C = g.channels;
     const int wc = (w + 1) / 2, hc = (h + 1) / 2;
-    return al((size_t)w * h * C * 4) * 2 + al((size_t)wc * hc * C * 4) + al((size_t)w * h);
+    const size_t n = (size_t)w * h;
+    const size_t part = (size_t)g.K * spk * gram_segments((int64_t)n) * gram_tiles(g) * 1024 * 4;
+    return al(n * C * 4) * 2 + al((size_t)wc * hc * C * 4) + al(n) * 2 + al(n * 4) * 2 + al(257 * 4) +
+           al(sort_tmp_bytes((int64_t)n)) + al(part);
 }
 
 mdn_status launch_to_planes(const mdn_image& im, float* out, int64_t row, int64_t plane, hipStream_t st) {
@@ -496,27 +575,47 @@ mdn_status train_accumulate(const mdn_gram& g, const mdn_image& z, const mdn_ima
     float* coarse = reinterpret_cast<float*>(p);
     p += al((size_t)Wc * Hc * C * 4);
     uint8_t* smap = reinterpret_cast<uint8_t*>(p);
+    p += al((size_t)W * H);
+    uint8_t* skeys = reinterpret_cast<uint8_t*>(p);
+    p += al((size_t)W * H);
+    int32_t* idx_in = reinterpret_cast<int32_t*>(p);
+    p += al((size_t)W * H * 4);
+    int32_t* idx = reinterpret_cast<int32_t*>(p);
+    p += al((size_t)W * H * 4);
+    int32_t* off = reinterpret_cast<int32_t*>(p);
+    p += al(257 * 4);
+    void* sort_tmp = p;
+    p += al(sort_tmp_bytes((int64_t)W * H));
+    float* part = reinterpret_cast<float*>(p);
     mdn_status s;
     if ((s = launch_to_planes(z, fine, W, (int64_t)W * H, st))) return s;
     if ((s = launch_to_planes(target, tgt, W, (int64_t)W * H, st))) return s;
     if (uc && (s = launch_to_planes(*uc, coarse, Wc, (int64_t)Wc * Hc, st))) return s;
     if ((s = launch_select_apply(z, nullptr, nullptr, W, smap, sel, nullptr, st))) return s;
+    const int64_t npx = (int64_t)W * H;
+    k_iota<<<256, 256, 0, st>>>(idx_in, npx);
+    if ((s = check_launch("iota"))) return s;
+    size_t tmp = sort_tmp_bytes(npx);
+    if (hipcub::DeviceRadixSort::SortPairs(sort_tmp, tmp, smap, skeys, idx_in, idx, (int)npx, 0, 8, st) != hipSuccess)
+        return fail(MDN_EDEVICE, "gram: bucket sort failed");
+    k_bucket_bounds<<<(g.K + 1 + 255) / 256, 256, 0, st>>>(skeys, npx, g.K, off);
+    if ((s = check_launch("bucket_bounds"))) return s;
 
     GramArgs a;
     memset(&a, 0, sizeof(a));
-    a.fine = fine;
-    a.coarse = coarse;
-    a.target = tgt;
+    a.planes = fine;
+    a.target_off = (int32_t)(tgt - fine);
+    a.coarse_off = (int32_t)(coarse - fine);
     a.f_row = W;
-    a.f_plane = (int64_t)W * H;
+    a.f_plane = W * H;
     a.c_row = Wc;
-    a.c_plane = (int64_t)Wc * Hc;
+    a.c_plane = Wc * Hc;
     a.W = W;
     a.H = H;
     a.Wc = Wc;
     a.Hc = Hc;
-    a.s = smap;
-    a.s_pitch = W;
+    a.idx = idx;
+    a.off = off;
     a.D = D;
     a.nrhs = nrhs;
     a.per_channel = g.layout == MDN_X_PER_CHANNEL;
@@ -535,18 +634,24 @@ mdn_status train_accumulate(const mdn_gram& g, const mdn_image& z, const mdn_ima
         for (int c = 0; c < C; ++c) a.feat[f++] = feat_pack(2, c, 0, 0);
     }
     a.Daug = f;
+    a.nseg = gram_segments((int64_t)W * H);
+    a.part = part;
     a.G = g.G;
     a.b = g.b;
     a.n = g.n;
     a.yy = g.yy;
     const int T = (f + 31) / 32;
-    dim3 grid(g.K, spk);
+    dim3 grid(g.K, spk, a.nseg);
+    bool launched = false;
 #define MDN_GRAM(P_, T_) \
-    if (precision == P_ && T == T_) { k_gram<P_, T_><<<grid, 256, 0, st>>>(a); return check_launch("gram"); }
+    if (!launched && precision == P_ && T == T_) { k_gram<P_, T_><<<grid, 256, 0, st>>>(a); launched = true; }
     MDN_GRAM(0, 1) MDN_GRAM(0, 2) MDN_GRAM(0, 3) MDN_GRAM(0, 4) MDN_GRAM(0, 5)
     MDN_GRAM(1, 1) MDN_GRAM(1, 2) MDN_GRAM(1, 3) MDN_GRAM(1, 4) MDN_GRAM(1, 5)
 #undef MDN_GRAM
-    return fail(MDN_ENOTSUP, "gram: %d features not supported", f);
+    if (!launched) return fail(MDN_ENOTSUP, "gram: %d features not supported", f);
+    if ((s = check_launch("gram"))) return s;
+    k_gram_reduce<<<dim3(g.K, spk), 256, 0, st>>>(a, T);
+    return check_launch("gram_reduce");
 }
 
 size_t solve_ws_bytes(const mdn_gram& g) {

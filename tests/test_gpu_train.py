@@ -99,6 +99,44 @@ def test_gram_multiscale_rgb(precision, tol):
     print(f"  worst ratio {worst:.3g}")
 
 
+@pytest.mark.parametrize("precision,tol", [(0, 2e-5), (1, 2e-4)])
+def test_gram_cross_channel_147(precision, tol):
+    """Cross-channel layout (x = the three channels' 7x7 patches, D = 147, three right-hand sides)
+    against the oracle's cross-channel normal equations; then the solved filters' output-space error
+    against the oracle's solution, relative to the target energy."""
+    import paper_1802_06130_amd as M
+    torch = _torch()
+    print(f"gram cross-channel precision={precision}", flush=True)
+    pairs = _pairs(3, 72, 3)
+    q_theta, t_s, t_c = 8, [0.03, 0.06], [0.25, 0.5]
+    K, C, D = q_theta * 9, 3, 147
+    st = O.CrossGramStats.zeros(K, C, D)
+    g = M.Gram(K, 3, 3, None, layout=M.X_CROSS_CHANNEL)
+    sel = M.Level(q_theta, t_s, t_c, 3, None, torch.zeros((K, 3, 49), device="cuda"), 3)
+    for z, u in pairs:
+        z64, u64 = z.astype(np.float64), u.astype(np.float64)
+        s = O.select(z64, q_theta, t_s, t_c)
+        O.accumulate_level_cross(st, s, O.to_filter_space(z64), O.to_filter_space(u64), 3)
+        M.train_accumulate(g, _dev(z), _dev(u), sel, precision=precision)
+    G = g.G.cpu().numpy().reshape(K, D, D)
+    b = g.b.cpu().numpy().reshape(K, C, D)
+    assert np.array_equal(g.n.cpu().numpy(), st.n), "sample counts differ"
+    diag = np.sqrt(np.maximum(np.einsum("kii->ki", st.G), 0.0))
+    ratio = np.abs(G - st.G) / (tol * diag[:, :, None] * diag[:, None, :] + 1e-12)
+    assert ratio.max() <= 1.0, f"G outside bound (worst ratio {ratio.max():.3g})"
+    yd = np.sqrt(np.maximum(st.yy, 0.0))
+    assert np.all(np.abs(b - st.b) <= tol * diag[:, None, :] * yd[:, :, None] + 1e-12)
+    lam = 1e-3
+    h_ref, fb = O.solve_level_cross(st, lam)
+    co, nfb = M.train_solve(g, lam)
+    assert nfb == int(fb.sum())
+    dh = co.double().cpu().numpy() - h_ref
+    err = sum(dh[k, c] @ st.G[k] @ dh[k, c] for k in range(K) for c in range(C))
+    rel = float(np.sqrt(err / st.yy.sum()))
+    print(f"  worst G ratio {ratio.max():.3g}; output-space rms error / target rms {rel:.3g}")
+    assert rel <= (1e-4 if precision == 0 else 1e-3)
+
+
 def test_solve_on_oracle_normal_equations():
     import paper_1802_06130_amd as M
     torch = _torch()

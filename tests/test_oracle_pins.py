@@ -406,6 +406,43 @@ def test_planted_single_scale_recovery_matches_lstsq():
     assert abs(res - ident) < 1e-9
 
 
+def test_planted_cross_channel_recovery_147_taps():
+    """Three-channel 7x7 patches (D = 147), three right-hand sides: planted filters are recovered at
+    lambda = 0, and one bucket's solution equals a library least-squares fit of its samples."""
+    rng = np.random.default_rng(45)
+    q_theta, r = 2, 3
+    K, C, D = q_theta * 2 * 2, 3, 147
+    planted = rng.normal(0, 0.2, (K, C, D))
+    zs = [rng.uniform(0, 1, (3, 60, 60)) for _ in range(5)]
+    st, co = (np.concatenate(v) for v in zip(*[O.level_features(z) for z in zs]))
+    t_s, t_c = [float(np.median(st))], [float(np.median(co))]
+    stats = O.CrossGramStats.zeros(K, C, D)
+    samples = []
+    for z in zs:
+        s = O.select(z, q_theta, t_s, t_c)
+        u = O.apply_level_cross(z, s, planted, r)
+        O.accumulate_level_cross(stats, s, z, u, r)
+        samples.append((s.ravel(), z, u))
+    h, fb = O.solve_level_cross(stats, 0.0)
+    assert not fb.any()
+    assert np.max(np.abs(h - planted)) < 1e-9
+    k = int(np.argmax(stats.n))
+    X = np.concatenate([np.concatenate([O.patch_matrix(z[c], r) for c in range(C)], axis=1)[s == k]
+                        for s, z, _ in samples])
+    for ch in range(C):
+        y = np.concatenate([u[ch].ravel()[s == k] for s, _, u in samples])
+        assert np.max(np.abs(np.linalg.lstsq(X, y, rcond=None)[0] - h[k, ch])) < 1e-9
+    # the per-channel layout is the special case of block-diagonal cross filters
+    diag = np.zeros((K, C, D))
+    for ch in range(C):
+        diag[:, ch, ch * 49:(ch + 1) * 49] = planted[:, ch, ch * 49:(ch + 1) * 49]
+    s0 = samples[0][0].reshape(60, 60)
+    want = np.stack([O.apply_level(zs[0][ch:ch + 1], s0, _bank_level(q_theta, t_s, t_c, r, None,
+                                                                     diag[:, ch:ch + 1, ch * 49:(ch + 1) * 49]))[0]
+                     for ch in range(C)])
+    assert np.max(np.abs(O.apply_level_cross(zs[0], s0, diag, r) - want)) < 1e-12
+
+
 def test_pooled_fallback_is_sum_of_bucket_statistics():
     rng = np.random.default_rng(43)
     K, C, D = 5, 1, 3
