@@ -43,6 +43,11 @@ constexpr int kRows = 14;              // coefficient rows per (bucket, channel)
 constexpr int kRowBytes = 16;          // 8 halves per row (7 taps + 0)
 constexpr int kBucketBytes = 3 * kRows * kRowBytes;   // 672
 constexpr int kMaxK = 160 * 1024 / kBucketBytes;      // 243 buckets fit in LDS
+// Bucket stride in LDS: 43 rows of 16 bytes (one padding row) when the bank still fits. All lanes
+// of a wave read the same (channel, row) of their own buckets; with an odd stride in 16-byte
+// units those reads spread over every group of four banks instead of half of them.
+constexpr int kPaddedBucketBytes = kBucketBytes + kRowBytes;   // 688
+int bank_stride(int K) { return (size_t)K * kPaddedBucketBytes <= 160 * 1024 ? kPaddedBucketBytes : kBucketBytes; }
 
 // lane i <- lane i+1 (shl) / lane i-1 (shr); the lane without a source reads 0 (bound_ctrl)
 __device__ __forceinline__ uint32_t shl1(uint32_t v) { return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x130, 0xF, 0xF, true); }
@@ -100,6 +105,7 @@ __global__ __launch_bounds__(64 * MDN_WALK_WAVES) void k_walk(WalkArgs a) {
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);     // wave-uniform
 
+    const int bstride = __builtin_amdgcn_readfirstlane(a.bank_stride);
     // ---- bank into LDS: row (k, c, r) = 7 taps + 0, float16
     {
         const int nrows = a.K * 3 * kRows;
@@ -116,7 +122,7 @@ __global__ __launch_bounds__(64 * MDN_WALK_WAVES) void k_walk(WalkArgs a) {
             q.y = pack2(v[2], v[3]);
             q.z = pack2(v[4], v[5]);
             q.w = c == 1 ? pack2(0.0f, v[6]) : pack2(v[6], 0.0f);
-            *reinterpret_cast<u4*>(bank + (size_t)i * kRowBytes) = q;
+            *reinterpret_cast<u4*>(bank + (size_t)k * bstride + (size_t)rem * kRowBytes) = q;
         }
     }
     __syncthreads();
@@ -251,7 +257,7 @@ __global__ __launch_bounds__(64 * MDN_WALK_WAVES) void k_walk(WalkArgs a) {
                 snext = ldo_u8(sb, (uint32_t)clampi(y + 1, 0, H - 1) * spitch + (uint32_t)xc);
                 float unext[3][3];
                 if constexpr (I & 1) load_coarse(((y + 1) >> 1) + 3, unext);
-                const uint8_t* bp = bank + (size_t)s * kBucketBytes;
+                const uint8_t* bp = bank + (size_t)s * bstride;
                 float acc[3];
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
@@ -296,7 +302,7 @@ bool walk_supported(const mdn_level& lvl, int channels) {
     return channels == 3 && lvl.radius_f == 3 && lvl.radius_g == 3 && lvl.q_theta * lvl.q_s * lvl.q_c <= kMaxK;
 }
 
-size_t walk_lds_bytes(int K) { return (size_t)K * kBucketBytes; }
+size_t walk_lds_bytes(int K) { return (size_t)K * bank_stride(K); }
 
 int device_cus() {
     int dev = 0, ncu = 256;
@@ -359,8 +365,10 @@ static mdn_status launch_typed_walk(const WalkArgs& a, int grid, size_t lds, hip
     return check_launch("walk");
 }
 
-mdn_status launch_walk_args(const WalkArgs& a, int zd, int ud, int od, hipStream_t st) {
-    if (a.n_strips <= 0) return MDN_OK;
+mdn_status launch_walk_args(const WalkArgs& args, int zd, int ud, int od, hipStream_t st) {
+    if (args.n_strips <= 0) return MDN_OK;
+    WalkArgs a = args;
+    a.bank_stride = bank_stride(a.K);
     const size_t lds = walk_lds_bytes(a.K);
     const int ncu = device_cus();
     const int blocks = (a.n_strips + kWaves - 1) / kWaves;

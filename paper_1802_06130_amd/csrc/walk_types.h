@@ -31,6 +31,7 @@ struct WalkArgs {
     int32_t n_imgs, n_strips;
     const void* coeffs;         // [K][3][98], float16 or float32
     int32_t coeff_dtype, K;
+    int32_t bank_stride;        // bytes between buckets in LDS (set by the launcher)
 };
 
 struct SelImage {
