@@ -80,13 +80,20 @@ __global__ __launch_bounds__(64 * kWaves) void k_down2_walk(D2Args a) {
         const uint32_t c0 = (uint32_t)clampi(2 * m, 0, im.Wi - 1), c1 = (uint32_t)clampi(2 * m + 1, 0, im.Wi - 1);
         const uint32_t irow = (uint32_t)im.i_row, ipl = (uint32_t)im.i_plane;
 
-        // horizontal pass of one input row (clamped) -> float64 (integer weights, exact)
-        auto hrow = [&](int r, double h[C]) {
+        // raw input pair (2m, 2m+1) of one input row (clamped), all channels
+        auto load = [&](int r, float e[C], float o[C]) {
             const uint32_t ro = (uint32_t)clampi(r, 0, im.Hi - 1) * irow;
 #pragma unroll
             for (int c = 0; c < C; ++c) {
-                const float e = ldo<TI>(im.in, ro + c * ipl + c0);    // column 2m
-                const float o = ldo<TI>(im.in, ro + c * ipl + c1);    // column 2m+1
+                e[c] = ldo<TI>(im.in, ro + c * ipl + c0);    // column 2m
+                o[c] = ldo<TI>(im.in, ro + c * ipl + c1);    // column 2m+1
+            }
+        };
+        // horizontal pass of one loaded row -> float64 (integer weights, exact)
+        auto hrow = [&](const float ev[C], const float ov[C], double h[C]) {
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const float e = ev[c], o = ov[c];
                 const float om1 = shr1f(o);          // 2m-1 (lane m-1)
                 const float em1 = shr1f(e);          // 2m-2
                 const float om2 = shr1f(om1);        // 2m-3 (lane m-2)
@@ -97,16 +104,34 @@ __global__ __launch_bounds__(64 * kWaves) void k_down2_walk(D2Args a) {
                        444.0 * (double)o + 116.0 * (double)ep1 - 36.0 * (double)op1 - 12.0 * (double)ep2;
             }
         };
-        // ring: input row 2*oy0 - 3 + k in slot k mod 8
+        // ring: input row 2*oy0 - 3 + k in slot k mod 8; the next output row's two input rows are
+        // loaded one step ahead of their use
         double ring[8][C];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) hrow(2 * oy0 - 3 + k, ring[k]);
+        for (int k = 0; k < 6; ++k) {
+            float e[C], o[C];
+            load(2 * oy0 - 3 + k, e, o);
+            hrow(e, o, ring[k]);
+        }
+        float ea[C], oa[C], eb[C], ob[C];
+        load(2 * oy0 + 3, ea, oa);
+        load(2 * oy0 + 4, eb, ob);
         for (int y0 = oy0; y0 < oy1; y0 += 4) {
             unroll([&](auto ic) {
                 constexpr int I = decltype(ic)::value;
                 const int oy = y0 + I;
-                hrow(2 * oy + 3, ring[(2 * I + 6) % 8]);
-                hrow(2 * oy + 4, ring[(2 * I + 7) % 8]);
+                float en[C], on[C], fn[C], pn[C];
+                load(2 * oy + 5, en, on);
+                load(2 * oy + 6, fn, pn);
+                hrow(ea, oa, ring[(2 * I + 6) % 8]);
+                hrow(eb, ob, ring[(2 * I + 7) % 8]);
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    ea[c] = en[c];
+                    oa[c] = on[c];
+                    eb[c] = fn[c];
+                    ob[c] = pn[c];
+                }
                 if (out_lane && oy < oy1) {
 #pragma unroll
                     for (int c = 0; c < C; ++c) {

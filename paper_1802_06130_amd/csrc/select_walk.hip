@@ -65,7 +65,13 @@ __device__ __forceinline__ void unroll(F&& f, std::integer_sequence<int, Is...>)
     (f(IC<Is>{}), ...);
 }
 
-__device__ __forceinline__ int bucket(double a, double b, double c, const SelWalkArgs& sp) {
+// Boundary directions of the orientation bins within the upper half plane, in LDS so that each
+// lane can index them (binary search).
+struct BoundaryTable {
+    double cs[kMaxTheta / 2], sn[kMaxTheta / 2];
+};
+
+__device__ __forceinline__ int bucket(double a, double b, double c, const SelWalkArgs& sp, const BoundaryTable& bt) {
     const double tr = a + c;
     const double dd = a - c;
     const double m2 = dd * dd + 4.0 * b * b;
@@ -87,8 +93,17 @@ __device__ __forceinline__ int bucket(double a, double b, double c, const SelWal
     } else {
         const bool upper = (Y > 0.0) || (Y == 0.0 && X > 0.0);
         const double px = upper ? X : -X, py = upper ? Y : -Y;
+        // boundary j (angle 2 pi (j+1) / q_theta) is passed iff its cross product with (px, py)
+        // is >= 0; the test is monotone in j, so count the passed ones by binary search
+        const int nb = sp.half - 1;
         int k = 0;
-        for (int j = 0; j < sp.half - 1; ++j) k += (sp.bcos[j] * py - sp.bsin[j] * px >= 0.0) ? 1 : 0;
+#pragma unroll
+        for (int step = 16; step >= 1; step >>= 1) {   // nb <= 31
+            const int j = k + step - 1;
+            const int jj = j < nb ? j : 0;
+            const bool pass = j < nb && (bt.cs[jj] * py - bt.sn[jj] * px >= 0.0);
+            k += pass ? step : 0;
+        }
         qt = k + (upper ? 0 : sp.half);
     }
     return (qt * sp.q_s + qs) * sp.q_c + qc;
@@ -98,6 +113,12 @@ template <typename TZ, int C>
 __global__ __launch_bounds__(64 * kWaves) void k_select_walk(SelWalkArgs a) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    __shared__ BoundaryTable bt;
+    for (int j = threadIdx.x; j < kMaxTheta / 2; j += 64 * kWaves) {
+        bt.cs[j] = a.bcos[j];
+        bt.sn[j] = a.bsin[j];
+    }
+    __syncthreads();
     for (int strip = blockIdx.x * kWaves + wave; strip < a.n_strips; strip += gridDim.x * kWaves) {
         SelImage im;
         if (a.imgs == nullptr) {
@@ -171,19 +192,22 @@ __global__ __launch_bounds__(64 * kWaves) void k_select_walk(SelWalkArgs a) {
 
         // ring: h(r) in hr[(r - ys) mod 5]; rows ys-2 .. ys+1 first
         P3 hr[5];
-        float z1[C], z2[C];
+        float z1[C], z2[C], z3[C], z4[C];
         hr[3] = hrow_at(ys - 2);
         hr[4] = hrow_at(ys - 1);
         hr[0] = hrow_at(ys);
         hr[1] = hrow_at(ys + 1);
         load(ys + 1, z1);
         load(ys + 2, z2);
+        load(ys + 3, z3);
+        load(ys + 4, z4);
         for (int y0 = ys; y0 < ye; y0 += 10) {
             unroll([&](auto ic) {
                 constexpr int I = decltype(ic)::value;
                 const int y = y0 + I;
-                float z3[C];
-                load(y + 3, z3);
+                // rows are loaded two steps before their use
+                float z5[C];
+                load(y + 5, z5);
                 // h(y+2): rows y+1, y+2, y+3; below the last image row it repeats h(H-1)
                 constexpr int slot = (I + 2) % 5;
                 constexpr int prev = (I + 1) % 5;
@@ -192,11 +216,13 @@ __global__ __launch_bounds__(64 * kWaves) void k_select_walk(SelWalkArgs a) {
                 for (int c = 0; c < C; ++c) {
                     z1[c] = z2[c];
                     z2[c] = z3[c];
+                    z3[c] = z4[c];
+                    z4[c] = z5[c];
                 }
                 const double sa = (((hr[0].A + hr[1].A) + hr[2].A) + hr[3].A) + hr[4].A;
                 const double sb = (((hr[0].B + hr[1].B) + hr[2].B) + hr[3].B) + hr[4].B;
                 const double sc = (((hr[0].C + hr[1].C) + hr[2].C) + hr[3].C) + hr[4].C;
-                const int s = bucket(sa, sb, sc, a);
+                const int s = bucket(sa, sb, sc, a, bt);
                 if (out_lane && y < ye) *((MDN_GLOBAL uint8_t*)im.s + (uint32_t)y * (uint32_t)im.s_pitch + (uint32_t)x) = (uint8_t)s;
             }, std::make_integer_sequence<int, 10>{});
         }
