@@ -186,7 +186,7 @@ void describe_cascade(const mdn_image& in, const mdn_image& out, void* ws, int L
         fill_walk_image(walk[l], a, l == L - 1 ? zl[L] : ul[l + 1], ul[l], 0);
         walk[l].s_map = smap;
         walk[l].s_pitch = a.width;
-        walk[l].rows = rows ? rows[l][2] : walk_rows(a.width, a.height, ncu * 4);
+        walk[l].rows = rows ? rows[l][2] : walk_rows(a.width, a.height, ncu * kWalkWaves);
     }
 }
 

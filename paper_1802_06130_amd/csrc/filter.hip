@@ -91,7 +91,8 @@ __device__ __forceinline__ int bucket_of(double a, double b, double c, const Sel
         const bool upper = (Y > 0.0) || (Y == 0.0 && X > 0.0);
         const double px = upper ? X : -X, py = upper ? Y : -Y;
         int k = 0;
-        for (int j = 0; j < half - 1; ++j) k += (sp.bcos[j] * py - sp.bsin[j] * px >= 0.0) ? 1 : 0;
+        // both products rounded alone (no fused multiply-add): an exact tie compares equal
+        for (int j = 0; j < half - 1; ++j) k += (__dmul_rn(sp.bcos[j], py) >= __dmul_rn(sp.bsin[j], px)) ? 1 : 0;
         qt = k + (upper ? 0 : half);
     }
     int qs = 0;
@@ -355,11 +356,28 @@ void fill_select_arg(const mdn_level& lvl, SelectArg& sa) {
     sa.q_c = lvl.q_c;
     for (int j = 0; j < lvl.q_s - 1; ++j) sa.t_s[j] = lvl.t_s[j];
     for (int j = 0; j < lvl.q_c - 1; ++j) sa.t_c[j] = lvl.t_c[j];
+    orientation_boundaries(lvl.q_theta, sa.bcos, sa.bsin);
+}
+
+void orientation_boundaries(int q_theta, double* bcos, double* bsin) {
     const double two_pi = 6.283185307179586476925286766559;
-    for (int k = 1; k < lvl.q_theta / 2; ++k) {
-        const double ang = two_pi * (double)k / (double)lvl.q_theta;
-        sa.bcos[k - 1] = cos(ang);
-        sa.bsin[k - 1] = sin(ang);
+    const int half = q_theta / 2;
+    for (int k = 1; k < half; ++k) {
+        const int m = half - k;             // mirror partner: angle pi - 2 pi k / q_theta
+        const int r = k < m ? k : m;        // the partner below the vertical
+        double c, s;
+        if (2 * k == half) {
+            c = 0.0;
+            s = 1.0;
+        } else if (4 * r == half) {
+            c = s = sqrt(0.5);
+        } else {
+            const double ang = two_pi * (double)r / (double)q_theta;
+            c = cos(ang);
+            s = sin(ang);
+        }
+        bcos[k - 1] = k < m ? c : -c;
+        bsin[k - 1] = s;
     }
 }
 

@@ -80,6 +80,12 @@ struct SelectArg {
 };
 
 void fill_select_arg(const mdn_level& lvl, SelectArg& a);
+// Directions (cos, sin) of the orientation-bin boundaries k = 1 .. q_theta/2 - 1 in the doubled-angle
+// plane (angle 2 pi k / q_theta), made exactly mirror-symmetric about the vertical: the boundary at
+// pi - x is (-cos x, sin x) bit for bit, the vertical one is (0, 1) and a diagonal one has equal
+// components. A vector lying exactly on a boundary then has a zero cross product with it and goes
+// to the upper bin, on either side of the vertical.
+void orientation_boundaries(int q_theta, double* bcos, double* bsin);
 
 // Launchers (stream work only; arguments already validated).
 mdn_status launch_down2_tiled(const mdn_image& in, const mdn_image& out, hipStream_t st);

@@ -13,7 +13,8 @@
 //   coherence: (sqrt(l1)-sqrt(l2))/(sqrt(l1)+sqrt(l2)) >= t  <=>  mu >= (2t / (1 + t^2)) tr   (tr > 0)
 //   orientation: the doubled-angle vector of the minor eigenvector, (c - a, -2b), against the bin
 //   boundary directions by cross products.
-// No LDS is used; about 140 registers per lane leave room for three waves per SIMD.
+// The only LDS use is a small table of bin boundary directions. The kernel is held to 128
+// registers per lane so that four waves share each SIMD and hide one another's latencies.
 
 #include "walk_types.h"
 
@@ -27,6 +28,9 @@ namespace mdn {
 namespace {
 
 constexpr int kLanesOut = kSelLanesOut;
+#ifndef MDN_SEL_WAVES_PER_SIMD
+#define MDN_SEL_WAVES_PER_SIMD 4
+#endif
 constexpr int kWaves = 4;
 
 __device__ __forceinline__ uint32_t shl1(uint32_t v) { return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x130, 0xF, 0xF, true); }
@@ -71,46 +75,68 @@ struct BoundaryTable {
     double cs[kMaxTheta / 2], sn[kMaxTheta / 2];
 };
 
+// QS, QC: strength and coherence bin counts when fixed at compile time (0: read from the arguments).
+// Orientation: with MQ > 0 (q_theta = 4 (MQ + 1)) the boundaries of the upper half plane are
+// symmetric about the vertical one, so the vector is folded into the first quadrant and tested
+// against the MQ boundaries below 90 degrees only (constants from the kernel arguments, no LDS, no
+// branches); with MQ = 0 the q_theta/2 - 1 boundaries are searched in NSTEP binary steps over the
+// LDS table (2^NSTEP > count).
+template <int QS, int QC, int MQ, int NSTEP>
 __device__ __forceinline__ int bucket(double a, double b, double c, const SelWalkArgs& sp, const BoundaryTable& bt) {
+    const int q_s = QS ? QS : sp.q_s, q_c = QC ? QC : sp.q_c;
     const double tr = a + c;
     const double dd = a - c;
     const double m2 = dd * dd + 4.0 * b * b;
     int qs = 0;
-    for (int j = 0; j < sp.q_s - 1; ++j) {
+#pragma unroll
+    for (int j = 0; j < (QS ? QS : kMaxThr + 1) - 1; ++j) {
+        if (!QS && j >= q_s - 1) break;
         const double d = 2.0 * sp.s_lim[j] - tr;
         qs += (d <= 0.0 || m2 >= d * d) ? 1 : 0;
     }
     int qc = 0;
     const double tr2 = tr * tr;
-    for (int j = 0; j < sp.q_c - 1; ++j) {
+#pragma unroll
+    for (int j = 0; j < (QC ? QC : kMaxThr + 1) - 1; ++j) {
+        if (!QC && j >= q_c - 1) break;
         const double k2 = sp.c_k2[j];
         qc += (k2 < 0.0 || (tr > 0.0 && m2 >= k2 * tr2)) ? 1 : 0;
     }
     const double X = c - a, Y = -2.0 * b;
-    int qt;
-    if (X == 0.0 && Y == 0.0) {
-        qt = sp.half;
-    } else {
-        const bool upper = (Y > 0.0) || (Y == 0.0 && X > 0.0);
-        const double px = upper ? X : -X, py = upper ? Y : -Y;
-        // boundary j (angle 2 pi (j+1) / q_theta) is passed iff its cross product with (px, py)
-        // is >= 0; the test is monotone in j, so count the passed ones by binary search
-        const int nb = sp.half - 1;
-        int k = 0;
+    // a zero vector (a = c, b = 0) has no orientation: it takes bin q_theta/2 (the oracle's theta = pi/2)
+    const bool flat = X == 0.0 && Y == 0.0;
+    const bool upper = (Y > 0.0) || (Y == 0.0 && X > 0.0);
+    const double px = upper ? X : -X, py = upper ? Y : -Y;
+    // boundary j (angle 2 pi (j+1) / q_theta) is passed iff its cross product with (px, py)
+    // is >= 0; the count of passed boundaries is the bin within the half plane. The two products
+    // are rounded alone (no fused multiply-add), so that an exact tie compares equal.
+    int k = 0;
+    if constexpr (MQ > 0) {
+        // The boundary table is exactly mirror-symmetric (the mirror of (c_j, s_j) is (-c_j, s_j) and
+        // the vertical one is (0, 1)), so this equals the test against every boundary:
+        // px >= 0: boundaries 0..MQ-1 are passed iff c_j py - s_j px >= 0, the vertical one iff
+        // px = 0, the mirrored ones never. px < 0: boundaries 0..MQ-1 and the vertical one always,
+        // mirrored boundary q_theta/2 - 2 - j iff -c_j py - s_j px >= 0.
+        const bool right = px >= 0.0;
+        const double spy = right ? py : -py;
 #pragma unroll
-        for (int step = 16; step >= 1; step >>= 1) {   // nb <= 31
+        for (int j = 0; j < MQ; ++j) k += (__dmul_rn(sp.bcos[j], spy) >= __dmul_rn(sp.bsin[j], px)) ? 1 : 0;
+        k += right ? (px == 0.0 ? 1 : 0) : MQ + 1;
+    } else {
+        const int nb = sp.half - 1;
+#pragma unroll
+        for (int step = 1 << (NSTEP - 1); step >= 1; step >>= 1) {
             const int j = k + step - 1;
             const int jj = j < nb ? j : 0;
-            const bool pass = j < nb && (bt.cs[jj] * py - bt.sn[jj] * px >= 0.0);
-            k += pass ? step : 0;
+            k += ((j < nb) & (__dmul_rn(bt.cs[jj], py) >= __dmul_rn(bt.sn[jj], px))) ? step : 0;
         }
-        qt = k + (upper ? 0 : sp.half);
     }
-    return (qt * sp.q_s + qs) * sp.q_c + qc;
+    const int qt = flat ? sp.half : k + (upper ? 0 : sp.half);
+    return (qt * q_s + qs) * q_c + qc;
 }
 
-template <typename TZ, int C>
-__global__ __launch_bounds__(64 * kWaves) void k_select_walk(SelWalkArgs a) {
+template <typename TZ, int C, int QS, int QC, int MQ, int NSTEP>
+__global__ __launch_bounds__(64 * kWaves, MDN_SEL_WAVES_PER_SIMD) void k_select_walk(SelWalkArgs a) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     __shared__ BoundaryTable bt;
@@ -190,39 +216,32 @@ __global__ __launch_bounds__(64 * kWaves) void k_select_walk(SelWalkArgs a) {
             return hrow(zu, zm, zd);
         };
 
-        // ring: h(r) in hr[(r - ys) mod 5]; rows ys-2 .. ys+1 first
+        // ring: h(r) in hr[(r - ys) mod 5]; rows ys-2 .. ys+1 first. Input rows r = ys+1 .. ys+5 sit
+        // in zr[(r - ys) mod 5] (fixed slots over the 10-row step body).
         P3 hr[5];
-        float z1[C], z2[C], z3[C], z4[C];
+        float zr[5][C];
         hr[3] = hrow_at(ys - 2);
         hr[4] = hrow_at(ys - 1);
         hr[0] = hrow_at(ys);
         hr[1] = hrow_at(ys + 1);
-        load(ys + 1, z1);
-        load(ys + 2, z2);
-        load(ys + 3, z3);
-        load(ys + 4, z4);
+        load(ys + 1, zr[1]);
+        load(ys + 2, zr[2]);
+        load(ys + 3, zr[3]);
+        load(ys + 4, zr[4]);
         for (int y0 = ys; y0 < ye; y0 += 10) {
             unroll([&](auto ic) {
                 constexpr int I = decltype(ic)::value;
                 const int y = y0 + I;
-                // rows are loaded two steps before their use
-                float z5[C];
-                load(y + 5, z5);
+                // rows are loaded two steps before their use; row y+5 replaces row y
+                load(y + 5, zr[I % 5]);
                 // h(y+2): rows y+1, y+2, y+3; below the last image row it repeats h(H-1)
                 constexpr int slot = (I + 2) % 5;
                 constexpr int prev = (I + 1) % 5;
-                hr[slot] = (y + 2 <= H - 1) ? hrow(z1, z2, z3) : hr[prev];
-#pragma unroll
-                for (int c = 0; c < C; ++c) {
-                    z1[c] = z2[c];
-                    z2[c] = z3[c];
-                    z3[c] = z4[c];
-                    z4[c] = z5[c];
-                }
+                hr[slot] = (y + 2 <= H - 1) ? hrow(zr[(I + 1) % 5], zr[(I + 2) % 5], zr[(I + 3) % 5]) : hr[prev];
                 const double sa = (((hr[0].A + hr[1].A) + hr[2].A) + hr[3].A) + hr[4].A;
                 const double sb = (((hr[0].B + hr[1].B) + hr[2].B) + hr[3].B) + hr[4].B;
                 const double sc = (((hr[0].C + hr[1].C) + hr[2].C) + hr[3].C) + hr[4].C;
-                const int s = bucket(sa, sb, sc, a, bt);
+                const int s = bucket<QS, QC, MQ, NSTEP>(sa, sb, sc, a, bt);
                 if (out_lane && y < ye) *((MDN_GLOBAL uint8_t*)im.s + (uint32_t)y * (uint32_t)im.s_pitch + (uint32_t)x) = (uint8_t)s;
             }, std::make_integer_sequence<int, 10>{});
         }
@@ -257,12 +276,7 @@ void fill_sel_consts(const mdn_level& lvl, SelWalkArgs& a) {
             a.c_k2[j] = k * k;
         }
     }
-    const double two_pi = 6.283185307179586476925286766559;
-    for (int k = 1; k < lvl.q_theta / 2; ++k) {
-        const double ang = two_pi * (double)k / (double)lvl.q_theta;
-        a.bcos[k - 1] = cos(ang);
-        a.bsin[k - 1] = sin(ang);
-    }
+    orientation_boundaries(lvl.q_theta, a.bcos, a.bsin);
 }
 
 mdn_status launch_select_args(const SelWalkArgs& a, int channels, int z_dtype, hipStream_t st) {
@@ -270,13 +284,22 @@ mdn_status launch_select_args(const SelWalkArgs& a, int channels, int z_dtype, h
     const int ncu = device_cus();
     const int blocks = (a.n_strips + kWaves - 1) / kWaves;
     const int grid = blocks < 8 * ncu ? blocks : 8 * ncu;
+    // 3 x 3 strength/coherence bins with 24 or 16 orientation bins get fixed-count instances
+    const int spec = (a.q_s == 3 && a.q_c == 3) ? (a.q_theta == 24 ? 1 : a.q_theta == 16 ? 2 : 0) : 0;
+#define MDN_SEL_LAUNCH(TZ_, C_)                                                                   \
+    do {                                                                                          \
+        if (spec == 1) k_select_walk<TZ_, C_, 3, 3, 5, 0><<<grid, 64 * kWaves, 0, st>>>(a);        \
+        else if (spec == 2) k_select_walk<TZ_, C_, 3, 3, 3, 0><<<grid, 64 * kWaves, 0, st>>>(a);   \
+        else k_select_walk<TZ_, C_, 0, 0, 0, 5><<<grid, 64 * kWaves, 0, st>>>(a);                  \
+    } while (0)
     if (channels == 3) {
-        if (z_dtype == MDN_F16) k_select_walk<_Float16, 3><<<grid, 64 * kWaves, 0, st>>>(a);
-        else k_select_walk<float, 3><<<grid, 64 * kWaves, 0, st>>>(a);
+        if (z_dtype == MDN_F16) MDN_SEL_LAUNCH(_Float16, 3);
+        else MDN_SEL_LAUNCH(float, 3);
     } else {
-        if (z_dtype == MDN_F16) k_select_walk<_Float16, 1><<<grid, 64 * kWaves, 0, st>>>(a);
-        else k_select_walk<float, 1><<<grid, 64 * kWaves, 0, st>>>(a);
+        if (z_dtype == MDN_F16) MDN_SEL_LAUNCH(_Float16, 1);
+        else MDN_SEL_LAUNCH(float, 1);
     }
+#undef MDN_SEL_LAUNCH
     return check_launch("select_walk");
 }
 

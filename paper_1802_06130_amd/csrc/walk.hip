@@ -26,10 +26,6 @@
 #include <type_traits>
 #include <utility>
 
-#ifndef MDN_WALK_WAVES
-#define MDN_WALK_WAVES 4
-#endif
-
 namespace mdn {
 
 namespace {
@@ -38,7 +34,7 @@ typedef _Float16 h2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u4 __attribute__((ext_vector_type(4)));
 
 constexpr int kLanesOut = kWalkLanesOut;
-constexpr int kWaves = MDN_WALK_WAVES;  // waves per workgroup
+constexpr int kWaves = kWalkWaves;     // waves per workgroup
 constexpr int kRows = 14;              // coefficient rows per (bucket, channel): 7 f + 7 g
 constexpr int kRowBytes = 16;          // 8 halves per row (7 taps + 0)
 constexpr int kBucketBytes = 3 * kRows * kRowBytes;   // 672

@@ -10,6 +10,10 @@ namespace mdn {
 constexpr int kWalkLanesOut = 58;   // filtering: output columns per wave (3-column halo each side)
 constexpr int kSelLanesOut = 58;    // selection: output columns per wave
 constexpr int kD2LanesOut = 60;     // pyramid: output columns per wave (2-column halo each side)
+#ifndef MDN_WALK_WAVES
+#define MDN_WALK_WAVES 8
+#endif
+constexpr int kWalkWaves = MDN_WALK_WAVES;   // filtering: waves per workgroup (one workgroup per CU)
 
 struct WalkImage {
     const void* z;          // RGB input of the level
