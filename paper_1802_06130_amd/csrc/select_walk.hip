@@ -220,10 +220,23 @@ __global__ __launch_bounds__(64 * kWaves, MDN_SEL_WAVES_PER_SIMD) void k_select_
         // in zr[(r - ys) mod 5] (fixed slots over the 10-row step body).
         P3 hr[5];
         float zr[5][C];
-        hr[3] = hrow_at(ys - 2);
-        hr[4] = hrow_at(ys - 1);
-        hr[0] = hrow_at(ys);
-        hr[1] = hrow_at(ys + 1);
+        // one row at a time (a rolled loop keeps the start-up within the register budget)
+#pragma unroll 1
+        for (int k = 0; k < 4; ++k) {
+            const P3 h = hrow_at(ys - 2 + k);
+            hr[0] = hr[1];
+            hr[1] = hr[2];
+            hr[2] = hr[3];
+            hr[3] = hr[4];
+            hr[4] = h;
+        }
+        {
+            const P3 h0 = hr[1], h1 = hr[2], h2 = hr[3], h3 = hr[4];   // rows ys-2 .. ys+1
+            hr[3] = h0;
+            hr[4] = h1;
+            hr[0] = h2;
+            hr[1] = h3;
+        }
         load(ys + 1, zr[1]);
         load(ys + 2, zr[2]);
         load(ys + 3, zr[3]);
