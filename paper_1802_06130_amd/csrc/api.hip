@@ -54,6 +54,10 @@ mdn_status check_image(const mdn_image* im, const char* name) {
     if (im->row_pitch < im->width) return fail(MDN_EINVAL, "%s: row_pitch < width", name);
     if (im->channels > 1 && im->plane_pitch < im->row_pitch * im->height)
         return fail(MDN_EINVAL, "%s: plane_pitch < height*row_pitch", name);
+    // kernels address an image with 32-bit byte offsets from its base
+    const int64_t extent = ((int64_t)(im->channels - 1) * im->plane_pitch + (int64_t)(im->height - 1) * im->row_pitch +
+                            im->width) * (im->dtype == MDN_F16 ? 2 : 4);
+    if (extent >= ((int64_t)1 << 31)) return fail(MDN_ENOTSUP, "%s: image spans 2 GiB or more", name);
     return MDN_OK;
 }
 
