@@ -69,6 +69,7 @@ def _level(**kw):
     (_img(data=0x1000), _level(radius_g=4), "radius_g"),
     (_img(data=0x1000), _level(channels=1), "channels"),
     (_img(data=0x1000), _level(coeffs=None), "coeffs"),
+    (B.MdnImage(0x1000, 8, 8, 3, M.F32, M.RGB, 0, 8, 1 << 28), _level(), "2 GiB"),
 ])
 def test_select_rejects_bad_arguments(img, lvl, msg):
     st = M.lib().mdn_select_filters(ct.byref(img), ct.byref(lvl), ct.c_void_p(0x2000), 8, None)
