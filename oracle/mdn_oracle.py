@@ -33,7 +33,7 @@ __all__ = [
     "thresholds_from_features", "level_features", "GramStats", "patch_matrix",
     "accumulate_level", "solve_level", "train_single", "train_multiscale",
     "CrossGramStats", "accumulate_level_cross", "solve_level_cross", "apply_level_cross",
-    "psnr", "round_storage",
+    "psnr", "round_storage", "dihedral", "augment_pairs",
 ]
 
 # --------------------------------------------------------------------------------------
@@ -569,9 +569,38 @@ def apply_level_cross(z_f: np.ndarray, s: np.ndarray, coeffs: np.ndarray, radius
     return out.reshape(C, H, W)
 
 
+# --------------------------------------------------------------------------------------
+# Training-set augmentation: Section 5 adds the axial flips and 90-degree rotations of
+# every noisy/clean pair so that the filters learn the symmetries.
+# Reading: all eight symmetries of the square (the dihedral group D4), numbered by three
+# bits applied in this order: bit 2 transposes (rows <-> columns), then bit 0 mirrors
+# the columns (x -> W-1-x) and bit 1 mirrors the rows (y -> H-1-y).
+# --------------------------------------------------------------------------------------
+
+def dihedral(img: np.ndarray, t: int) -> np.ndarray:
+    """Symmetry t (0..7) of the square applied to the last two axes of img."""
+    x = np.asarray(img)
+    if t & 4:
+        x = np.swapaxes(x, -1, -2)
+    if t & 1:
+        x = x[..., :, ::-1]
+    if t & 2:
+        x = x[..., ::-1, :]
+    return np.ascontiguousarray(x)
+
+
+def augment_pairs(pairs):
+    """Every pair followed by its seven other symmetries (the same symmetry on both images)."""
+    return [(dihedral(z, t), dihedral(u, t)) for z, u in pairs for t in range(8)]
+
+
 def train_single(pairs, q_theta: int, q_s: int, q_c: int, radius: int, lam: float,
-                 t_s=None, t_c=None, n_min=None):
-    """Single-scale bank (Eq. (1), (7)-(8)) from (noisy, clean) pairs of (C, H, W) images."""
+                 t_s=None, t_c=None, n_min=None, augment: bool = False):
+    """Single-scale bank (Eq. (1), (7)-(8)) from (noisy, clean) pairs of (C, H, W) images.
+
+    augment: train on the eight symmetries of every pair (Section 5)."""
+    if augment:
+        pairs = augment_pairs(pairs)
     zs = [np.asarray(z, dtype=np.float64) for z, _ in pairs]
     if t_s is None or t_c is None:
         feats = [level_features(z) for z in zs]
@@ -593,14 +622,18 @@ def train_single(pairs, q_theta: int, q_s: int, q_c: int, radius: int, lam: floa
 
 def train_multiscale(pairs, n_trained_levels: int, q_theta: int, q_s: int, q_c: int,
                      radius_f: int, radius_g: int, lam: float, thresholds=None, n_min=None,
-                     storage=None):
+                     storage=None, augment: bool = False):
     """Multiscale bank, trained from the second-coarsest level down (Section 4).
 
     Level l is fitted with u^{l+1} = the output of the already trained level l+1
     on the same pair (u^L = z^L); targets are the clean pyramid levels.
     ``thresholds``: optional list (per level) of (t_s, t_c); otherwise the
     equal-population quantiles of each level's training features.
+    ``augment``: train on the eight symmetries of every pair (Section 5); each
+    symmetric copy is a pair of its own, with its own pyramid and cascade.
     """
+    if augment:
+        pairs = augment_pairs(pairs)
     L = n_trained_levels
     pz = [build_pyramid(z, L + 1, storage) for z, _ in pairs]
     pu = [build_pyramid(u, L + 1, storage) for _, u in pairs]

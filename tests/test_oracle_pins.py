@@ -525,3 +525,57 @@ def test_thresholds_equal_population():
     t = O.thresholds_from_features(v, 3)
     counts = [(v < t[0]).sum(), ((v >= t[0]) & (v < t[1])).sum(), (v >= t[1]).sum()]
     assert max(counts) - min(counts) <= 2
+
+
+# ----------------------------------------------------------------------------- augmentation (Section 5)
+
+def test_dihedral_transforms_form_the_group_of_the_square():
+    rng = np.random.default_rng(11)
+    x = rng.random((2, 5, 7))                         # generic: no symmetry of its own
+    imgs = [O.dihedral(x, t) for t in range(8)]
+    # eight distinct images, each a rearrangement of the same pixels
+    for i in range(8):
+        assert np.array_equal(np.sort(imgs[i].ravel()), np.sort(x.ravel()))
+        for j in range(i):
+            assert imgs[i].shape != imgs[j].shape or not np.array_equal(imgs[i], imgs[j])
+    # closed under composition, each row of the composition table a permutation (a group)
+    def index_of(y):
+        hits = [t for t in range(8) if imgs[t].shape == y.shape and np.array_equal(imgs[t], y)]
+        assert len(hits) == 1
+        return hits[0]
+    table = np.array([[index_of(O.dihedral(imgs[a], b)) for b in range(8)] for a in range(8)])
+    for row in table:
+        assert sorted(row) == list(range(8))
+    # quarter turns against numpy's rotation (an independent definition): order 4; mirrors: order 2
+    assert np.array_equal(imgs[5], np.rot90(x, -1, axes=(1, 2)))
+    assert np.array_equal(imgs[6], np.rot90(x, 1, axes=(1, 2)))
+    y = x
+    for _ in range(4):
+        y = O.dihedral(y, 5)
+    assert np.array_equal(y, x)
+    for t in (1, 2, 4):
+        assert np.array_equal(O.dihedral(O.dihedral(x, t), t), x)
+
+
+def test_augmented_training_depends_only_on_the_orbit():
+    """Training on the eight symmetries of a pair equals training on those of any symmetric copy of
+    it: the same eight images in another order, so only the FP64 summation order differs. A set of
+    transforms that is not the whole group (a missing or repeated symmetry) breaks this."""
+    pairs = [synth.noisy_pair(40 + i, 24, 24, 3, 25) for i in range(2)]
+    pairs = [(z.astype(np.float64), u.astype(np.float64)) for z, u in pairs]
+    ref, _, _ = O.train_single(pairs, 8, 2, 2, 1, 1e-3, augment=True)
+    for t in (1, 5, 6):
+        moved = [(O.dihedral(z, t), O.dihedral(u, t)) for z, u in pairs]
+        got, _, _ = O.train_single(moved, 8, 2, 2, 1, 1e-3, augment=True)
+        assert np.max(np.abs(got.levels[0].coeffs - ref.levels[0].coeffs)) < 1e-9
+        plain_ref, _, _ = O.train_single(pairs, 8, 2, 2, 1, 1e-3)
+        plain_got, _, _ = O.train_single(moved, 8, 2, 2, 1, 1e-3)
+        assert np.max(np.abs(plain_got.levels[0].coeffs - plain_ref.levels[0].coeffs)) > 1e-3
+    # multiscale: each symmetric copy has its own pyramid and cascade
+    pairs = [synth.noisy_pair(50, 32, 32, 3, 25)]
+    pairs = [(z.astype(np.float64), u.astype(np.float64)) for z, u in pairs]
+    ref, _, _ = O.train_multiscale(pairs, 2, 8, 2, 2, 1, 1, 1e-3, augment=True)
+    moved = [(O.dihedral(z, 6), O.dihedral(u, 6)) for z, u in pairs]
+    got, _, _ = O.train_multiscale(moved, 2, 8, 2, 2, 1, 1, 1e-3, augment=True)
+    for a, b in zip(ref.levels, got.levels):
+        assert np.max(np.abs(a.coeffs - b.coeffs)) < 1e-9
