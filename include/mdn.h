@@ -104,6 +104,14 @@ typedef struct {
 mdn_status mdn_pyramid_build(const mdn_image* level0, int32_t n_out, const mdn_image* out,
                              void* stream);
 
+/* Training-set augmentation (Section 5: the axial flips and 90-degree rotations of every
+ * training pair are added so that the filters learn the symmetries).
+ * out = symmetry `transform` (0..7) of the square applied to every plane of in: bit 2 transposes
+ * (first), then bit 0 mirrors the columns (x -> w-1-x) and bit 1 mirrors the rows. out must be
+ * h x w when bit 2 is set (w x h otherwise), with the channels, dtype and colour of in, and must
+ * not alias it. Elements are moved bit for bit. */
+mdn_status mdn_dihedral(const mdn_image* in, int32_t transform, const mdn_image* out, void* stream);
+
 /* Filter selector s(i) (Section 3, "Filter selection"; Eq. (6); features as in mdn_level).
  * z: RGB or grey image of the level. s_out: device uint8 [height][s_pitch]. */
 mdn_status mdn_select_filters(const mdn_image* z, const mdn_level* lvl, uint8_t* s_out,

@@ -62,6 +62,7 @@ def lib() -> ct.CDLL:
         P = ct.POINTER
         sig = {
             "mdn_pyramid_build": [P(MdnImage), i32, P(MdnImage), vp],
+            "mdn_dihedral": [P(MdnImage), i32, P(MdnImage), vp],
             "mdn_select_filters": [P(MdnImage), P(MdnLevel), vp, i64, vp],
             "mdn_apply_level": [P(MdnImage), P(MdnImage), vp, i64, P(MdnLevel), P(MdnImage), vp, vp],
             "mdn_denoise_workspace_size": [i32, i32, i32, i32, i32, P(ct.c_size_t)],
@@ -171,6 +172,24 @@ def pyramid_build(level0, n_out: int, storage=None, out=None):
     descs = (MdnImage * max(1, n_out))(*[image(o, color) for o in out])
     _check(lib().mdn_pyramid_build(ct.byref(image(level0, color)), n_out, descs, _stream_ptr()))
     return out
+
+
+def dihedral(img, transform: int, out=None):
+    """Symmetry ``transform`` (0..7) of the square applied to every plane of ``img`` (C, H, W):
+    bit 2 transposes (first), bit 0 mirrors the columns, bit 1 the rows (Section 5)."""
+    torch = _torch()
+    C, H, W = img.shape
+    if out is None:
+        shape = (C, W, H) if transform & 4 else (C, H, W)
+        out = torch.empty(shape, dtype=img.dtype, device=img.device)
+    color = GRAY if C == 1 else RGB
+    _check(lib().mdn_dihedral(ct.byref(image(img, color)), int(transform), ct.byref(image(out, color)), _stream_ptr()))
+    return out
+
+
+def augment_pairs(pairs):
+    """Every (noisy, clean) pair followed by its seven other symmetries, made on the GPU."""
+    return [(dihedral(z, t), dihedral(u, t)) for z, u in pairs for t in range(8)]
 
 
 def select_filters(z, level: Level, out=None):
@@ -368,9 +387,12 @@ def level_thresholds(zs, q_s: int, q_c: int):
 
 
 def train_single(pairs, q_theta: int, q_s: int, q_c: int, radius: int, lam: float, thresholds=None,
-                 precision: int = GRAM_F32, coeff_dtype=None, min_count=None):
-    """Single-scale bank (Eq. (1), (7)-(8)) from (noisy, clean) (C, H, W) device tensors."""
+                 precision: int = GRAM_F32, coeff_dtype=None, min_count=None, augment: bool = False):
+    """Single-scale bank (Eq. (1), (7)-(8)) from (noisy, clean) (C, H, W) device tensors;
+    augment: train on the eight symmetries of every pair (Section 5)."""
     torch = _torch()
+    if augment:
+        pairs = augment_pairs(pairs)
     C = pairs[0][0].shape[0]
     if thresholds is None:
         t_s, t_c = level_thresholds([z for z, _ in pairs], q_s, q_c)
@@ -389,10 +411,13 @@ def train_single(pairs, q_theta: int, q_s: int, q_c: int, radius: int, lam: floa
 
 def train_multiscale(pairs, n_trained_levels: int, q_theta: int, q_s: int, q_c: int, radius_f: int,
                      radius_g: int, lam: float, thresholds=None, precision: int = GRAM_F32, coeff_dtype=None,
-                     min_count=None, storage=None):
+                     min_count=None, storage=None, augment: bool = False):
     """Multiscale bank trained from the second-coarsest level down (Section 4); pairs are
-    (noisy, clean) (C, H, W) device tensors. Returns (Bank, grams, fallback counts)."""
+    (noisy, clean) (C, H, W) device tensors. Returns (Bank, grams, fallback counts).
+    augment: train on the eight symmetries of every pair (Section 5), each its own pair."""
     torch = _torch()
+    if augment:
+        pairs = augment_pairs(pairs)
     L = n_trained_levels
     C = pairs[0][0].shape[0]
     dev = pairs[0][0].device

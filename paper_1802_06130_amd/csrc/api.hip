@@ -166,6 +166,21 @@ mdn_status mdn_pyramid_build(const mdn_image* level0, int32_t n_out, const mdn_i
     return MDN_OK;
 }
 
+mdn_status mdn_dihedral(const mdn_image* in, int32_t transform, const mdn_image* out, void* stream) {
+    g_err[0] = 0;
+    mdn_status st = check_image(in, "in");
+    if (st) return st;
+    if ((st = check_image(out, "out"))) return st;
+    if (transform < 0 || transform > 7) return fail(MDN_EINVAL, "transform must be in [0, 7], got %d", transform);
+    const int w = (transform & 4) ? in->height : in->width, h = (transform & 4) ? in->width : in->height;
+    if (out->width != w || out->height != h)
+        return fail(MDN_EINVAL, "out must be %d x %d, got %d x %d", w, h, out->width, out->height);
+    if (out->channels != in->channels || out->dtype != in->dtype || out->color != in->color)
+        return fail(MDN_EINVAL, "out: channels, dtype and colour must equal the input's");
+    if (!empty(*in) && in->data == out->data) return fail(MDN_EINVAL, "out must not alias in");
+    return launch_dihedral(*in, *out, transform, static_cast<hipStream_t>(stream));
+}
+
 mdn_status mdn_select_filters(const mdn_image* z, const mdn_level* lvl, uint8_t* s_out, int64_t s_pitch,
                               void* stream) {
     g_err[0] = 0;

@@ -101,6 +101,7 @@ bool walk_supported(const mdn_level& lvl, int channels);
 mdn_status launch_walk(const mdn_image& z, const mdn_image& uc, const mdn_level& lvl, const mdn_image& out,
                        const uint8_t* s_in, uint8_t* s_buf, int64_t s_pitch, hipStream_t st);
 mdn_status launch_select_walk(const mdn_image& z, const mdn_level& lvl, uint8_t* s, int64_t s_pitch, hipStream_t st);
+mdn_status launch_dihedral(const mdn_image& in, const mdn_image& out, int t, hipStream_t st);
 mdn_status launch_features(const mdn_image& z, double* strength, double* coherence, hipStream_t st);
 
 // training

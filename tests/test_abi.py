@@ -112,3 +112,19 @@ def test_library_missing_fails_loudly(tmp_path, monkeypatch):
     monkeypatch.setattr(B, "_lib", None)
     with pytest.raises(RuntimeError, match="not built"):
         B.lib()
+
+
+@pytest.mark.parametrize("t,out_wh,alias,msg", [
+    (8, (8, 6), False, "transform"),
+    (-1, (8, 6), False, "transform"),
+    (4, (8, 6), False, "must be 6 x 8"),
+    (1, (6, 8), False, "must be 8 x 6"),
+    (0, (8, 6), True, "alias"),
+])
+def test_dihedral_rejects_bad_arguments(t, out_wh, alias, msg):
+    src = B.MdnImage(0x1000, 8, 6, 3, M.F32, M.RGB, 0, 8, 48)
+    w, h = out_wh
+    dst = B.MdnImage(0x1000 if alias else 0x9000, w, h, 3, M.F32, M.RGB, 0, w, w * h)
+    st = M.lib().mdn_dihedral(ct.byref(src), t, ct.byref(dst), None)
+    assert st == B.MDN_EINVAL
+    assert msg in M.lib().mdn_last_error().decode()
