@@ -25,7 +25,7 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 __all__ = [
-    "KR", "KB", "rgb_to_ycc", "ycc_to_rgb", "to_filter_space", "from_filter_space",
+    "KR", "KB", "KG", "rgb_to_ycc", "ycc_to_rgb", "to_filter_space", "from_filter_space",
     "keys_cubic", "down2_weights", "down2", "build_pyramid",
     "shift", "coarse_shift", "gradients", "structure_tensor", "eigen_features",
     "quantize", "select", "select_margins", "tap_offsets",
@@ -33,7 +33,7 @@ __all__ = [
     "thresholds_from_features", "level_features", "GramStats", "patch_matrix",
     "accumulate_level", "solve_level", "train_single", "train_multiscale",
     "CrossGramStats", "accumulate_level_cross", "solve_level_cross", "apply_level_cross",
-    "psnr", "round_storage", "dihedral", "augment_pairs",
+    "psnr", "round_storage", "dihedral", "augment_pairs", "luma", "selector_image",
 ]
 
 # --------------------------------------------------------------------------------------
@@ -272,12 +272,36 @@ def select_margins(a, b, c, theta, strength, coherence, q_theta, t_s, t_c):
     return np.minimum(np.minimum(m_theta, m_s), m_c)
 
 
-def select(z_sel: np.ndarray, q_theta: int, t_s, t_c, return_margin: bool = False):
+def luma(rgb: np.ndarray) -> np.ndarray:
+    """BT.601 luma Y = Kr R + Kg G + Kb B of an RGB (3, H, W) image, as a (1, H, W) image
+    (the first row of the colour matrix of the footnote of Section 3)."""
+    rgb = np.asarray(rgb, dtype=np.float64)
+    return (KR * rgb[0] + KG * rgb[1] + KB * rgb[2])[None]
+
+
+def selector_image(z_sel: np.ndarray, selector: str = "rgb") -> np.ndarray:
+    """The image whose structure tensor selects the filters.
+
+    "rgb": the colour image itself, the channels summed in Eq. (6) (the paper's choice).
+    "luma": its luma channel alone, the structure tensor of the earlier methods that Section 3
+    compares against (Fig. 2: luma alone can miss structure that is visible in colour).
+    Grey images are their own luma.
+    """
+    z_sel = np.asarray(z_sel, dtype=np.float64)
+    if selector == "luma" and z_sel.shape[0] == 3:
+        return luma(z_sel)
+    if selector not in ("rgb", "luma"):
+        raise ValueError(selector)
+    return z_sel
+
+
+def select(z_sel: np.ndarray, q_theta: int, t_s, t_c, return_margin: bool = False, selector: str = "rgb"):
     """Filter selector s(i) from the image the structure tensor is taken on.
 
-    Colour images: z_sel is RGB (the channels summed in Eq. (6)); grey: one channel.
+    Colour images: z_sel is RGB (the channels summed in Eq. (6)), or its luma with
+    selector="luma"; grey: one channel.
     """
-    a, b, c = structure_tensor(z_sel)
+    a, b, c = structure_tensor(selector_image(z_sel, selector))
     theta, strength, coh = eigen_features(a, b, c)
     s = quantize(theta, strength, coh, q_theta, t_s, t_c)
     if return_margin:
@@ -307,6 +331,7 @@ class LevelBank:
     radius_g: int
     radius_f: Optional[int]
     coeffs: np.ndarray
+    selector: str = "rgb"          # "rgb" (Eq. (6) over R, G, B) or "luma"
 
     @property
     def q_s(self):
@@ -368,7 +393,7 @@ def denoise(img: np.ndarray, bank: Bank, storage=None, return_index_maps: bool =
     img = round_storage(img, storage)
     if not multiscale:
         lb = bank.levels[0]
-        s = select(img, lb.q_theta, lb.t_s, lb.t_c)
+        s = select(img, lb.q_theta, lb.t_s, lb.t_c, selector=lb.selector)
         out = from_filter_space(apply_level(to_filter_space(img), s, lb))
         out = round_storage(out, storage)
         return (out, [s]) if return_index_maps else out
@@ -377,7 +402,7 @@ def denoise(img: np.ndarray, bank: Bank, storage=None, return_index_maps: bool =
     maps = [None] * L
     for lev in range(L - 1, -1, -1):
         lb = bank.levels[lev]
-        s = select(pyr[lev], lb.q_theta, lb.t_s, lb.t_c)
+        s = select(pyr[lev], lb.q_theta, lb.t_s, lb.t_c, selector=lb.selector)
         maps[lev] = s
         u = apply_level(to_filter_space(pyr[lev]), s, lb, u_coarse=u)
         if lev > 0:
@@ -391,9 +416,9 @@ def denoise(img: np.ndarray, bank: Bank, storage=None, return_index_maps: bool =
 # trained level by level from the second-coarsest level down (Section 4).
 # --------------------------------------------------------------------------------------
 
-def level_features(z_sel: np.ndarray):
+def level_features(z_sel: np.ndarray, selector: str = "rgb"):
     """(strength, coherence) of every pixel, flattened."""
-    a, b, c = structure_tensor(z_sel)
+    a, b, c = structure_tensor(selector_image(z_sel, selector))
     _, strength, coh = eigen_features(a, b, c)
     return strength.ravel(), coh.ravel()
 
@@ -595,15 +620,16 @@ def augment_pairs(pairs):
 
 
 def train_single(pairs, q_theta: int, q_s: int, q_c: int, radius: int, lam: float,
-                 t_s=None, t_c=None, n_min=None, augment: bool = False):
+                 t_s=None, t_c=None, n_min=None, augment: bool = False, selector: str = "rgb"):
     """Single-scale bank (Eq. (1), (7)-(8)) from (noisy, clean) pairs of (C, H, W) images.
 
-    augment: train on the eight symmetries of every pair (Section 5)."""
+    augment: train on the eight symmetries of every pair (Section 5).
+    selector: structure tensor of the colour image ("rgb") or of its luma ("luma")."""
     if augment:
         pairs = augment_pairs(pairs)
     zs = [np.asarray(z, dtype=np.float64) for z, _ in pairs]
     if t_s is None or t_c is None:
-        feats = [level_features(z) for z in zs]
+        feats = [level_features(z, selector) for z in zs]
         st = np.concatenate([f[0] for f in feats])
         co = np.concatenate([f[1] for f in feats])
         t_s = thresholds_from_features(st, q_s) if t_s is None else np.asarray(t_s, float)
@@ -613,16 +639,16 @@ def train_single(pairs, q_theta: int, q_s: int, q_c: int, radius: int, lam: floa
     D = (2 * radius + 1) ** 2
     stats = GramStats.zeros(K, C, D)
     for (z, u) in pairs:
-        s = select(np.asarray(z, np.float64), q_theta, t_s, t_c)
+        s = select(np.asarray(z, np.float64), q_theta, t_s, t_c, selector=selector)
         accumulate_level(stats, s, to_filter_space(z), to_filter_space(u), radius)
     coeffs, fb = solve_level(stats, lam, n_min)
-    lb = LevelBank(q_theta, np.asarray(t_s, float), np.asarray(t_c, float), radius, None, coeffs)
+    lb = LevelBank(q_theta, np.asarray(t_s, float), np.asarray(t_c, float), radius, None, coeffs, selector)
     return Bank([lb]), stats, fb
 
 
 def train_multiscale(pairs, n_trained_levels: int, q_theta: int, q_s: int, q_c: int,
                      radius_f: int, radius_g: int, lam: float, thresholds=None, n_min=None,
-                     storage=None, augment: bool = False):
+                     storage=None, augment: bool = False, selector: str = "rgb"):
     """Multiscale bank, trained from the second-coarsest level down (Section 4).
 
     Level l is fitted with u^{l+1} = the output of the already trained level l+1
@@ -631,6 +657,7 @@ def train_multiscale(pairs, n_trained_levels: int, q_theta: int, q_s: int, q_c: 
     equal-population quantiles of each level's training features.
     ``augment``: train on the eight symmetries of every pair (Section 5); each
     symmetric copy is a pair of its own, with its own pyramid and cascade.
+    ``selector``: structure tensor of the colour levels ("rgb") or of their luma ("luma").
     """
     if augment:
         pairs = augment_pairs(pairs)
@@ -646,7 +673,7 @@ def train_multiscale(pairs, n_trained_levels: int, q_theta: int, q_s: int, q_c: 
         if thresholds is not None:
             t_s, t_c = (np.asarray(t, float) for t in thresholds[lev])
         else:
-            feats = [level_features(p[lev]) for p in pz]
+            feats = [level_features(p[lev], selector) for p in pz]
             t_s = thresholds_from_features(np.concatenate([f[0] for f in feats]), q_s)
             t_c = thresholds_from_features(np.concatenate([f[1] for f in feats]), q_c)
         K = q_theta * q_s * q_c
@@ -654,12 +681,12 @@ def train_multiscale(pairs, n_trained_levels: int, q_theta: int, q_s: int, q_c: 
         stats = GramStats.zeros(K, C, D)
         smaps = []
         for i in range(len(pairs)):
-            s = select(pz[i][lev], q_theta, t_s, t_c)
+            s = select(pz[i][lev], q_theta, t_s, t_c, selector=selector)
             smaps.append(s)
             accumulate_level(stats, s, to_filter_space(pz[i][lev]), to_filter_space(pu[i][lev]),
                              radius_g, radius_f, uhat[i])
         coeffs, fb = solve_level(stats, lam, n_min)
-        lb = LevelBank(q_theta, t_s, t_c, radius_g, radius_f, coeffs)
+        lb = LevelBank(q_theta, t_s, t_c, radius_g, radius_f, coeffs, selector)
         levels[lev] = lb
         stats_all[lev] = stats
         fallbacks[lev] = fb

@@ -579,3 +579,57 @@ def test_augmented_training_depends_only_on_the_orbit():
     got, _, _ = O.train_multiscale(moved, 2, 8, 2, 2, 1, 1, 1e-3, augment=True)
     for a, b in zip(ref.levels, got.levels):
         assert np.max(np.abs(a.coeffs - b.coeffs)) < 1e-9
+
+
+# ----------------------------------------------------------------------------- luma-only selector (Section 3, Fig. 2)
+
+def test_luma_of_grey_is_the_grey_value():
+    """The published luma weights sum to one: a grey pixel (v, v, v) has luma v."""
+    v = np.random.default_rng(5).random((1, 9, 11))
+    y = O.luma(np.concatenate([v, v, v]))
+    assert y.shape == (1, 9, 11)
+    assert np.max(np.abs(y - v)) <= 2 * np.finfo(float).eps
+    assert abs(O.KR + O.KG + O.KB - 1.0) <= np.finfo(float).eps
+
+
+@pytest.mark.parametrize("slopes", [((0.01, 0.0), (0.0, 0.02), (0.004, 0.004)),
+                                    ((-0.006, 0.013), (0.011, 0.004), (0.0, -0.01))])
+def test_luma_selector_on_colour_ramps(slopes):
+    """Channels with different ramps: the luma is the ramp with the luma-weighted slope, whose
+    orientation and strength the luma selector reports (coherence 1), while the colour tensor
+    sums the three channels' tensors."""
+    H, W = 20, 24
+    z = np.concatenate([_ramp(H, W, a, b, 1) for a, b in slopes])
+    K = np.array([O.KR, O.KG, O.KB])
+    al = float(K @ [s[0] for s in slopes])
+    be = float(K @ [s[1] for s in slopes])
+    core = (slice(3, H - 3), slice(3, W - 3))
+    a, b, c = O.structure_tensor(O.selector_image(z, "luma"))
+    theta, strength, coh = O.eigen_features(a, b, c)
+    want = np.mod(np.arctan2(be, al) + np.pi / 2, np.pi)
+    d = np.abs(theta[core] - want)
+    assert np.max(np.minimum(d, np.pi - d)) < 1e-7
+    assert np.max(np.abs(strength[core] - np.hypot(al, be))) < 1e-14
+    assert np.min(coh[core]) > 1 - 1e-6
+    a2, b2, c2 = O.structure_tensor(z)
+    assert np.max(np.abs(a2[core] - sum(s[0] ** 2 for s in slopes))) < 1e-15
+    assert np.max(np.abs(b2[core] - sum(s[0] * s[1] for s in slopes))) < 1e-15
+
+
+def test_luma_misses_an_equal_luma_colour_edge():
+    """Section 3 / Fig. 2: an edge between two colours of (nearly) equal luma is invisible to the
+    luma structure tensor and strong in the colour one."""
+    c1 = np.array([0.9, 0.3, 0.5])
+    y1 = O.KR * c1[0] + O.KG * c1[1] + O.KB * c1[2]
+    c2 = np.array([0.2, 0.6, 0.0])
+    c2[2] = (y1 - O.KR * c2[0] - O.KG * c2[1]) / O.KB
+    z = np.empty((3, 16, 16))
+    z[:, :, :8] = c1[:, None, None]
+    z[:, :, 8:] = c2[:, None, None]
+    t_s, t_c = [0.01, 0.05], [0.3, 0.6]
+    _, s_rgb, _ = O.eigen_features(*O.structure_tensor(z))
+    _, s_luma, _ = O.eigen_features(*O.structure_tensor(O.selector_image(z, "luma")))
+    assert s_rgb[8, 8] > 0.1 and np.max(s_luma) < 1e-12
+    q = O.select(z, 8, t_s, t_c, selector="luma") // 3 % 3   # strength bin
+    assert np.all(q == 0)
+    assert O.select(z, 8, t_s, t_c)[8, 8] // 3 % 3 == 2
