@@ -49,6 +49,11 @@ typedef enum { MDN_F32 = 0, MDN_F16 = 1 } mdn_dtype;
  * always taken on RGB. */
 typedef enum { MDN_GRAY = 0, MDN_RGB = 1, MDN_YCC = 2 } mdn_color;
 
+/* Image the structure tensor of the filter selector is taken on (Section 3): the colour image,
+ * its channels summed as in Eq. (6) (the paper's choice), or its luma alone. Grey images are
+ * their own luma. */
+typedef enum { MDN_SELECT_RGB = 0, MDN_SELECT_LUMA = 1 } mdn_selector;
+
 typedef struct {
     void*   data;         /* device pointer */
     int32_t width;
@@ -68,7 +73,9 @@ typedef struct {
  *   q_s_bin:     number of t_s thresholds that sqrt(lambda1) reaches (>=);
  *   q_c_bin:     number of t_c thresholds that (sqrt(l1)-sqrt(l2))/(sqrt(l1)+sqrt(l2)) reaches.
  * The structure tensor sums, over the RGB (or grey) channels, products of central-difference
- * gradients averaged over a 5x5 box (Eq. (6)); it is evaluated in float64.
+ * gradients averaged over a 5x5 box (Eq. (6)); it is evaluated in float64. With
+ * selector = MDN_SELECT_LUMA it is taken on the BT.601 luma Y = 0.299 R + 0.587 G + 0.114 B of a
+ * colour level instead (float64; the luma-only analysis Section 3 compares against, Fig. 2).
  * coeffs[k][c] holds taps_f = (2*radius_f+1)^2 upscale taps applied to the coarser output at
  * floor(i/2) + j, then taps_g = (2*radius_g+1)^2 taps applied to this level's input at i + j,
  * both row-major over (dy, dx). */
@@ -80,7 +87,7 @@ typedef struct {
     int32_t radius_g;     /* 1, 2 or 3 */
     int32_t channels;     /* 1 or 3, must match the images */
     int32_t coeff_dtype;  /* mdn_dtype of coeffs */
-    int32_t reserved;     /* must be 0 */
+    int32_t selector;     /* mdn_selector: MDN_SELECT_RGB (0) or MDN_SELECT_LUMA (1) */
     const double* t_s;    /* HOST, q_s-1 ascending strength thresholds */
     const double* t_c;    /* HOST, q_c-1 ascending coherence thresholds */
     const void*   coeffs; /* DEVICE, [K][channels][taps_f + taps_g] */
@@ -212,8 +219,9 @@ mdn_status mdn_train_solve(const mdn_gram* g, double lambda, int64_t min_count, 
                            void* stream);
 
 /* Per-pixel strength sqrt(lambda1) and coherence of z's structure tensor (as used by the
- * selector), float64, dense [height][width] device arrays. */
-mdn_status mdn_level_features(const mdn_image* z, double* strength, double* coherence, void* stream);
+ * selector: `selector` is an mdn_selector), float64, dense [height][width] device arrays. */
+mdn_status mdn_level_features(const mdn_image* z, int32_t selector, double* strength, double* coherence,
+                              void* stream);
 
 /* Equal-population thresholds: the k/q quantiles (k = 1..q-1, linear interpolation between order
  * statistics) of n device doubles, written to out_host[q-1]. Synchronises `stream`. */

@@ -21,6 +21,7 @@ HEADER_PATH = os.path.join(os.path.dirname(_PKG), "include", "mdn.h")
 MDN_OK, MDN_EINVAL, MDN_ENOMEM, MDN_EDEVICE, MDN_ENOTSUP, MDN_ETIMEOUT, MDN_ECANCELED = range(7)
 F32, F16 = 0, 1
 GRAY, RGB, YCC = 0, 1, 2
+SELECT_RGB, SELECT_LUMA = 0, 1       # mdn_selector
 _STATUS = {1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOTSUP", 5: "ETIMEOUT", 6: "ECANCELED"}
 
 
@@ -39,7 +40,7 @@ class MdnImage(ct.Structure):
 class MdnLevel(ct.Structure):
     _fields_ = [("q_theta", ct.c_int32), ("q_s", ct.c_int32), ("q_c", ct.c_int32),
                 ("radius_f", ct.c_int32), ("radius_g", ct.c_int32), ("channels", ct.c_int32),
-                ("coeff_dtype", ct.c_int32), ("reserved", ct.c_int32),
+                ("coeff_dtype", ct.c_int32), ("selector", ct.c_int32),
                 ("t_s", ct.POINTER(ct.c_double)), ("t_c", ct.POINTER(ct.c_double)),
                 ("coeffs", ct.c_void_p)]
 
@@ -125,8 +126,9 @@ class Level:
     """One trained level: thresholds on the host, coefficients on the device."""
 
     def __init__(self, q_theta: int, t_s: Sequence[float], t_c: Sequence[float], radius_g: int,
-                 radius_f: Optional[int], coeffs, channels: int):
+                 radius_f: Optional[int], coeffs, channels: int, selector: int = 0):
         self.q_theta = int(q_theta)
+        self.selector = int(selector)          # SELECT_RGB or SELECT_LUMA
         self.t_s = np.ascontiguousarray(np.asarray(t_s, dtype=np.float64))
         self.t_c = np.ascontiguousarray(np.asarray(t_c, dtype=np.float64))
         self.radius_g = int(radius_g)
@@ -142,7 +144,7 @@ class Level:
 
     def desc(self) -> MdnLevel:
         return MdnLevel(self.q_theta, len(self.t_s) + 1, len(self.t_c) + 1, self.radius_f, self.radius_g,
-                        self.channels, _dtype_code(self.coeffs), 0,
+                        self.channels, _dtype_code(self.coeffs), self.selector,
                         ct.cast(self._ts_arr, ct.POINTER(ct.c_double)),
                         ct.cast(self._tc_arr, ct.POINTER(ct.c_double)),
                         ct.c_void_p(self.coeffs.data_ptr()))
@@ -272,7 +274,7 @@ def _train_sigs(L):
                                  ct.c_size_t, vp],
         "mdn_train_solve_workspace_size": [P(MdnGram), P(ct.c_size_t)],
         "mdn_train_solve": [P(MdnGram), ct.c_double, i64, vp, i32, vp, vp, ct.c_size_t, vp],
-        "mdn_level_features": [P(MdnImage), vp, vp, vp],
+        "mdn_level_features": [P(MdnImage), i32, vp, vp, vp],
         "mdn_quantiles_workspace_size": [i64, P(ct.c_size_t)],
         "mdn_quantiles": [vp, i64, i32, P(ct.c_double), vp, ct.c_size_t, vp],
     }
@@ -349,15 +351,16 @@ def train_solve(gram: Gram, lam: float, min_count: Optional[int] = None, coeff_d
     return out, int(nfb.item())
 
 
-def level_features(z):
-    """(strength, coherence) float64 device tensors [H][W] of the RGB/grey image z."""
+def level_features(z, selector: int = 0):
+    """(strength, coherence) float64 device tensors [H][W] of the RGB/grey image z (structure tensor
+    of the colour image, or of its luma with selector=SELECT_LUMA)."""
     torch = _torch()
     _train_sigs(lib())
     C, H, W = z.shape
     st = torch.empty((H, W), dtype=torch.float64, device=z.device)
     co = torch.empty((H, W), dtype=torch.float64, device=z.device)
-    _check(lib().mdn_level_features(ct.byref(image(z)), ct.c_void_p(st.data_ptr()), ct.c_void_p(co.data_ptr()),
-                                    _stream_ptr()))
+    _check(lib().mdn_level_features(ct.byref(image(z)), int(selector), ct.c_void_p(st.data_ptr()),
+                                    ct.c_void_p(co.data_ptr()), _stream_ptr()))
     return st, co
 
 
@@ -375,10 +378,10 @@ def quantiles(values, q: int) -> np.ndarray:
     return np.array(list(out))
 
 
-def level_thresholds(zs, q_s: int, q_c: int):
+def level_thresholds(zs, q_s: int, q_c: int, selector: int = 0):
     """Equal-population strength / coherence thresholds over the given level images."""
     torch = _torch()
-    feats = [level_features(z) for z in zs]
+    feats = [level_features(z, selector) for z in zs]
     st = torch.cat([f[0].view(-1) for f in feats])
     co = torch.cat([f[1].view(-1) for f in feats])
     t_s = quantiles(st, q_s) if q_s > 1 else np.zeros(0)
@@ -387,34 +390,37 @@ def level_thresholds(zs, q_s: int, q_c: int):
 
 
 def train_single(pairs, q_theta: int, q_s: int, q_c: int, radius: int, lam: float, thresholds=None,
-                 precision: int = GRAM_F32, coeff_dtype=None, min_count=None, augment: bool = False):
+                 precision: int = GRAM_F32, coeff_dtype=None, min_count=None, augment: bool = False,
+                 selector: int = 0):
     """Single-scale bank (Eq. (1), (7)-(8)) from (noisy, clean) (C, H, W) device tensors;
-    augment: train on the eight symmetries of every pair (Section 5)."""
+    augment: train on the eight symmetries of every pair (Section 5); selector: SELECT_RGB or
+    SELECT_LUMA."""
     torch = _torch()
     if augment:
         pairs = augment_pairs(pairs)
     C = pairs[0][0].shape[0]
     if thresholds is None:
-        t_s, t_c = level_thresholds([z for z, _ in pairs], q_s, q_c)
+        t_s, t_c = level_thresholds([z for z, _ in pairs], q_s, q_c, selector)
     else:
         t_s, t_c = thresholds
     K = q_theta * (len(t_s) + 1) * (len(t_c) + 1)
     dummy = torch.zeros((K, C, (2 * radius + 1) ** 2), dtype=torch.float32, device=pairs[0][0].device)
-    sel = Level(q_theta, t_s, t_c, radius, None, dummy, C)
+    sel = Level(q_theta, t_s, t_c, radius, None, dummy, C, selector)
     g = Gram(K, C, radius, None, device=pairs[0][0].device)
     ws = None
     for z, u in pairs:
         ws = train_accumulate(g, z, u, sel, precision=precision, ws=ws)
     co, nfb = train_solve(g, lam, min_count, coeff_dtype)
-    return Bank([Level(q_theta, t_s, t_c, radius, None, co, C)]), g, nfb
+    return Bank([Level(q_theta, t_s, t_c, radius, None, co, C, selector)]), g, nfb
 
 
 def train_multiscale(pairs, n_trained_levels: int, q_theta: int, q_s: int, q_c: int, radius_f: int,
                      radius_g: int, lam: float, thresholds=None, precision: int = GRAM_F32, coeff_dtype=None,
-                     min_count=None, storage=None, augment: bool = False):
+                     min_count=None, storage=None, augment: bool = False, selector: int = 0):
     """Multiscale bank trained from the second-coarsest level down (Section 4); pairs are
     (noisy, clean) (C, H, W) device tensors. Returns (Bank, grams, fallback counts).
-    augment: train on the eight symmetries of every pair (Section 5), each its own pair."""
+    augment: train on the eight symmetries of every pair (Section 5), each its own pair;
+    selector: SELECT_RGB (colour structure tensor) or SELECT_LUMA."""
     torch = _torch()
     if augment:
         pairs = augment_pairs(pairs)
@@ -433,15 +439,16 @@ def train_multiscale(pairs, n_trained_levels: int, q_theta: int, q_s: int, q_c: 
         if thresholds is not None:
             t_s, t_c = thresholds[lev]
         else:
-            t_s, t_c = level_thresholds([p[lev] for p in pz], q_s, q_c)
+            t_s, t_c = level_thresholds([p[lev] for p in pz], q_s, q_c, selector)
         K = q_theta * (len(t_s) + 1) * (len(t_c) + 1)
-        sel = Level(q_theta, t_s, t_c, radius_g, radius_f, torch.zeros((K, C, D), dtype=torch.float32, device=dev), C)
+        sel = Level(q_theta, t_s, t_c, radius_g, radius_f, torch.zeros((K, C, D), dtype=torch.float32, device=dev), C,
+                    selector)
         g = Gram(K, C, radius_g, radius_f, device=dev)
         for i in range(len(pairs)):
             ws = train_accumulate(g, pz[i][lev], pu[i][lev], sel, u_coarse=uhat[i], precision=precision,
                                   coarse_color=coarse_color, ws=ws)
         co, nfb = train_solve(g, lam, min_count, coeff_dtype)
-        lvl = Level(q_theta, t_s, t_c, radius_g, radius_f, co, C)
+        lvl = Level(q_theta, t_s, t_c, radius_g, radius_f, co, C, selector)
         levels[lev], grams[lev], fbs[lev] = lvl, g, nfb
         uhat = [apply_level(pz[i][lev], lvl, u_coarse=uhat[i], coarse_color=coarse_color,
                             out_dtype=pz[i][lev].dtype) for i in range(len(pairs))]

@@ -63,7 +63,8 @@ mdn_status check_image(const mdn_image* im, const char* name) {
 
 mdn_status check_level(const mdn_level* lv, int channels) {
     if (!lv) return fail(MDN_EINVAL, "level: null");
-    if (lv->reserved != 0) return fail(MDN_EINVAL, "level: reserved field must be 0");
+    if (lv->selector != MDN_SELECT_RGB && lv->selector != MDN_SELECT_LUMA)
+        return fail(MDN_EINVAL, "level: selector must be MDN_SELECT_RGB or MDN_SELECT_LUMA");
     if (lv->q_theta < 2 || lv->q_theta > kMaxTheta || (lv->q_theta & 1))
         return fail(MDN_EINVAL, "level: q_theta must be even in [2, %d]", kMaxTheta);
     if (lv->q_s < 1 || lv->q_s > kMaxThr || lv->q_c < 1 || lv->q_c > kMaxThr)
@@ -395,14 +396,17 @@ mdn_status mdn_train_solve(const mdn_gram* g, double lambda, int64_t min_count, 
     return train_solve(*g, lambda, min_count, coeffs, coeff_dtype, n_fallback, ws, static_cast<hipStream_t>(stream));
 }
 
-mdn_status mdn_level_features(const mdn_image* z, double* strength, double* coherence, void* stream) {
+mdn_status mdn_level_features(const mdn_image* z, int32_t selector, double* strength, double* coherence,
+                              void* stream) {
     g_err[0] = 0;
     mdn_status st = check_image(z, "z");
     if (st) return st;
+    if (selector != MDN_SELECT_RGB && selector != MDN_SELECT_LUMA)
+        return fail(MDN_EINVAL, "selector must be MDN_SELECT_RGB or MDN_SELECT_LUMA");
     if (z->color == MDN_YCC) return fail(MDN_EINVAL, "z: pass RGB or grey");
     if (empty(*z)) return MDN_OK;
     if (!strength || !coherence) return fail(MDN_EINVAL, "null output");
-    return launch_features(*z, strength, coherence, static_cast<hipStream_t>(stream));
+    return launch_features(*z, selector == MDN_SELECT_LUMA, strength, coherence, static_cast<hipStream_t>(stream));
 }
 
 mdn_status mdn_quantiles_workspace_size(int64_t n, size_t* bytes) {

@@ -4,7 +4,8 @@
 //  1. The tile's input window plus a 3-pixel halo (clamped at the image border) is staged in
 //     LDS as float32 (RGB or grey).
 //  2. Selection, in float64: per position of the tile plus a 2-pixel halo, the central-difference
-//     gradients of every channel give A = sum_c gx^2, B = sum_c gx gy, C = sum_c gy^2 (evaluated at
+//     gradients of every channel (or of the luma alone, for luma-selector levels) give
+//     A = sum_c gx^2, B = sum_c gx gy, C = sum_c gy^2 (evaluated at
 //     the clamped position, so the box reads replicated border values); a 5 x 5 box mean (a
 //     horizontal then a vertical 5-sum in LDS) gives the tensor (a, b, c); its eigen-features are
 //     binned into s(i). The orientation bin is found without atan2: the doubled-angle vector of
@@ -145,13 +146,23 @@ __global__ __launch_bounds__(256) void k_select_apply(FilterArgs a) {
             const int lyd = clampi(yc + 1, 0, H - 1) - (y0 - kHalo);
             const int lyu = clampi(yc - 1, 0, H - 1) - (y0 - kHalo);
             double A = 0.0, B = 0.0, Cc = 0.0;
+            if (C == 3 && a.sel.luma) {
+                // luma-only structure tensor: gradients of Y at the four neighbours
+                auto Y = [&](int yy, int xx) { return luma_d(zs[0][yy][xx], zs[1][yy][xx], zs[C - 1][yy][xx]); };
+                const double gx = (Y(ly, lxr) - Y(ly, lxl)) * 0.5;
+                const double gy = (Y(lyd, lx) - Y(lyu, lx)) * 0.5;
+                A = gx * gx;
+                B = gx * gy;
+                Cc = gy * gy;
+            } else {
 #pragma unroll
-            for (int c = 0; c < C; ++c) {
-                const double gx = ((double)zs[c][ly][lxr] - (double)zs[c][ly][lxl]) * 0.5;
-                const double gy = ((double)zs[c][lyd][lx] - (double)zs[c][lyu][lx]) * 0.5;
-                A += gx * gx;
-                B += gx * gy;
-                Cc += gy * gy;
+                for (int c = 0; c < C; ++c) {
+                    const double gx = ((double)zs[c][ly][lxr] - (double)zs[c][ly][lxl]) * 0.5;
+                    const double gy = ((double)zs[c][lyd][lx] - (double)zs[c][lyu][lx]) * 0.5;
+                    A += gx * gx;
+                    B += gx * gy;
+                    Cc += gy * gy;
+                }
             }
             pa[r][q] = A;
             pb[r][q] = B;
@@ -330,10 +341,11 @@ mdn_status dispatch_radii(const FilterArgs& fa, bool apply, int rf, int rg, int 
 
 }  // namespace
 
-mdn_status launch_features(const mdn_image& z, double* strength, double* coherence, hipStream_t st) {
+mdn_status launch_features(const mdn_image& z, int luma, double* strength, double* coherence, hipStream_t st) {
     if (z.width == 0 || z.height == 0) return MDN_OK;
     FilterArgs fa;
     memset(&fa, 0, sizeof(fa));
+    fa.sel.luma = luma && z.channels == 3;
     fa.z = ImageArg{z.data, z.row_pitch, z.plane_pitch, z.width, z.height};
     fa.z_dtype = z.dtype;
     fa.feat_s = strength;
@@ -354,6 +366,7 @@ void fill_select_arg(const mdn_level& lvl, SelectArg& sa) {
     sa.q_theta = lvl.q_theta;
     sa.q_s = lvl.q_s;
     sa.q_c = lvl.q_c;
+    sa.luma = lvl.selector == MDN_SELECT_LUMA && lvl.channels == 3;
     for (int j = 0; j < lvl.q_s - 1; ++j) sa.t_s[j] = lvl.t_s[j];
     for (int j = 0; j < lvl.q_c - 1; ++j) sa.t_c[j] = lvl.t_c[j];
     orientation_boundaries(lvl.q_theta, sa.bcos, sa.bsin);

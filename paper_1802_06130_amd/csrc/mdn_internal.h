@@ -68,9 +68,16 @@ constexpr int kMaxTheta = 64;     // max orientation bins
 constexpr int kMaxFeat = 160;     // max regression features incl. targets (training)
 
 // Selector constants, passed by value.
+// BT.601 luma in float64, products and sums rounded one at a time in a fixed order
+// ((Kr R + Kg G) + Kb B), so every kernel gets the same value for the same pixel.
+constexpr double kLumaR = 0.299, kLumaB = 0.114, kLumaG = 1.0 - kLumaR - kLumaB;
+__device__ __forceinline__ double luma_d(double r, double g, double b) {
+    return __dadd_rn(__dadd_rn(__dmul_rn(kLumaR, r), __dmul_rn(kLumaG, g)), __dmul_rn(kLumaB, b));
+}
+
 struct SelectArg {
     int32_t q_theta, q_s, q_c;
-    int32_t pad;
+    int32_t luma;               // colour input: structure tensor of the luma only
     double t_s[kMaxThr];
     double t_c[kMaxThr];
     // Unit vectors at the orientation-bin boundaries of the doubled angle, k = 1 .. q_theta/2 - 1,
@@ -102,7 +109,7 @@ mdn_status launch_walk(const mdn_image& z, const mdn_image& uc, const mdn_level&
                        const uint8_t* s_in, uint8_t* s_buf, int64_t s_pitch, hipStream_t st);
 mdn_status launch_select_walk(const mdn_image& z, const mdn_level& lvl, uint8_t* s, int64_t s_pitch, hipStream_t st);
 mdn_status launch_dihedral(const mdn_image& in, const mdn_image& out, int t, hipStream_t st);
-mdn_status launch_features(const mdn_image& z, double* strength, double* coherence, hipStream_t st);
+mdn_status launch_features(const mdn_image& z, int luma, double* strength, double* coherence, hipStream_t st);
 
 // training
 int gram_dims(const mdn_gram& g, int* D, int* nrhs, int* sys_per_k);

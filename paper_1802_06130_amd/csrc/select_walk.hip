@@ -45,6 +45,10 @@ __device__ __forceinline__ double shr1d(double v) {
     const uint64_t u = (uint64_t)__double_as_longlong(v);
     return __longlong_as_double((long long)(((uint64_t)shr1((uint32_t)(u >> 32)) << 32) | shr1((uint32_t)u)));
 }
+__device__ __forceinline__ float shl1x(float v) { return shl1f(v); }
+__device__ __forceinline__ float shr1x(float v) { return shr1f(v); }
+__device__ __forceinline__ double shl1x(double v) { return shl1d(v); }
+__device__ __forceinline__ double shr1x(double v) { return shr1d(v); }
 __device__ __forceinline__ double readlane_d(double v, int lane) {
     const uint64_t u = (uint64_t)__double_as_longlong(v);
     const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, lane);
@@ -135,8 +139,11 @@ __device__ __forceinline__ int bucket(double a, double b, double c, const SelWal
     return (qt * q_s + qs) * q_c + qc;
 }
 
-template <typename TZ, int C, int QS, int QC, int MQ, int NSTEP>
+template <typename TZ, int C, bool LUMA, int QS, int QC, int MQ, int NSTEP>
 __global__ __launch_bounds__(64 * kWaves, MDN_SEL_WAVES_PER_SIMD) void k_select_walk(SelWalkArgs a) {
+    static_assert(!LUMA || C == 3, "the luma selector reads RGB");
+    constexpr int NC = LUMA ? 1 : C;                             // channels of the selector image
+    using RowT = std::conditional_t<LUMA, double, float>;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     __shared__ BoundaryTable bt;
@@ -170,17 +177,22 @@ __global__ __launch_bounds__(64 * kWaves, MDN_SEL_WAVES_PER_SIMD) void k_select_
         const TZ* zb = static_cast<const TZ*>(im.z);
         const uint32_t zrow = (uint32_t)im.z_row, zpl = (uint32_t)im.z_plane;
 
-        auto load = [&](int row, float v[C]) {
+        // a row of the selector image: the channels as loaded, or the float64 luma of RGB
+        auto load = [&](int row, RowT v[NC]) {
             const uint32_t o = (uint32_t)clampi(row, 0, H - 1) * zrow + (uint32_t)xc;
+            if constexpr (LUMA) {
+                v[0] = luma_d(ldo(zb, o), ldo(zb, o + zpl), ldo(zb, o + 2 * zpl));
+            } else {
 #pragma unroll
-            for (int c = 0; c < C; ++c) v[c] = ldo(zb, o + c * zpl);
+                for (int c = 0; c < C; ++c) v[c] = ldo(zb, o + c * zpl);
+            }
         };
         // horizontally summed products at an in-image row from its rows (above, centre, below)
-        auto hrow = [&](const float zu[C], const float zm[C], const float zd[C]) {
+        auto hrow = [&](const RowT zu[NC], const RowT zm[NC], const RowT zd[NC]) {
             P3 p{0.0, 0.0, 0.0};
 #pragma unroll
-            for (int c = 0; c < C; ++c) {
-                const double dx = (double)shl1f(zm[c]) - (double)shr1f(zm[c]);
+            for (int c = 0; c < NC; ++c) {
+                const double dx = (double)shl1x(zm[c]) - (double)shr1x(zm[c]);
                 const double dy = (double)zd[c] - (double)zu[c];
                 p.A += dx * dx;
                 p.B += dx * dy;
@@ -209,7 +221,7 @@ __global__ __launch_bounds__(64 * kWaves, MDN_SEL_WAVES_PER_SIMD) void k_select_
         };
         auto hrow_at = [&](int r) {      // row cl(r), loading its three input rows
             const int c = clampi(r, 0, H - 1);
-            float zu[C], zm[C], zd[C];
+            RowT zu[NC], zm[NC], zd[NC];
             load(c - 1, zu);
             load(c, zm);
             load(c + 1, zd);
@@ -219,7 +231,7 @@ __global__ __launch_bounds__(64 * kWaves, MDN_SEL_WAVES_PER_SIMD) void k_select_
         // ring: h(r) in hr[(r - ys) mod 5]; rows ys-2 .. ys+1 first. Input rows r = ys+1 .. ys+5 sit
         // in zr[(r - ys) mod 5] (fixed slots over the 10-row step body).
         P3 hr[5];
-        float zr[5][C];
+        RowT zr[5][NC];
         // one row at a time (a rolled loop keeps the start-up within the register budget)
 #pragma unroll 1
         for (int k = 0; k < 4; ++k) {
@@ -276,6 +288,7 @@ void fill_sel_consts(const mdn_level& lvl, SelWalkArgs& a) {
     a.q_s = lvl.q_s;
     a.q_c = lvl.q_c;
     a.half = lvl.q_theta / 2;
+    a.luma = lvl.selector == MDN_SELECT_LUMA && lvl.channels == 3;
     for (int j = 0; j < lvl.q_s - 1; ++j) {
         const double t = lvl.t_s[j] > 0.0 ? lvl.t_s[j] : 0.0;
         a.s_lim[j] = 100.0 * t * t;
@@ -299,18 +312,21 @@ mdn_status launch_select_args(const SelWalkArgs& a, int channels, int z_dtype, h
     const int grid = blocks < 8 * ncu ? blocks : 8 * ncu;
     // 3 x 3 strength/coherence bins with 24 or 16 orientation bins get fixed-count instances
     const int spec = (a.q_s == 3 && a.q_c == 3) ? (a.q_theta == 24 ? 1 : a.q_theta == 16 ? 2 : 0) : 0;
-#define MDN_SEL_LAUNCH(TZ_, C_)                                                                   \
-    do {                                                                                          \
-        if (spec == 1) k_select_walk<TZ_, C_, 3, 3, 5, 0><<<grid, 64 * kWaves, 0, st>>>(a);        \
-        else if (spec == 2) k_select_walk<TZ_, C_, 3, 3, 3, 0><<<grid, 64 * kWaves, 0, st>>>(a);   \
-        else k_select_walk<TZ_, C_, 0, 0, 0, 5><<<grid, 64 * kWaves, 0, st>>>(a);                  \
+#define MDN_SEL_LAUNCH(TZ_, C_, L_)                                                                 \
+    do {                                                                                               \
+        if (spec == 1) k_select_walk<TZ_, C_, L_, 3, 3, 5, 0><<<grid, 64 * kWaves, 0, st>>>(a);         \
+        else if (spec == 2) k_select_walk<TZ_, C_, L_, 3, 3, 3, 0><<<grid, 64 * kWaves, 0, st>>>(a);    \
+        else k_select_walk<TZ_, C_, L_, 0, 0, 0, 5><<<grid, 64 * kWaves, 0, st>>>(a);                   \
     } while (0)
-    if (channels == 3) {
-        if (z_dtype == MDN_F16) MDN_SEL_LAUNCH(_Float16, 3);
-        else MDN_SEL_LAUNCH(float, 3);
+    if (channels == 3 && a.luma) {
+        if (z_dtype == MDN_F16) MDN_SEL_LAUNCH(_Float16, 3, true);
+        else MDN_SEL_LAUNCH(float, 3, true);
+    } else if (channels == 3) {
+        if (z_dtype == MDN_F16) MDN_SEL_LAUNCH(_Float16, 3, false);
+        else MDN_SEL_LAUNCH(float, 3, false);
     } else {
-        if (z_dtype == MDN_F16) MDN_SEL_LAUNCH(_Float16, 1);
-        else MDN_SEL_LAUNCH(float, 1);
+        if (z_dtype == MDN_F16) MDN_SEL_LAUNCH(_Float16, 1, false);
+        else MDN_SEL_LAUNCH(float, 1, false);
     }
 #undef MDN_SEL_LAUNCH
     return check_launch("select_walk");

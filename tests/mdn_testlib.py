@@ -16,13 +16,14 @@ TOL_F16 = 2e-3       # max-abs, float16 storage
 
 @functools.lru_cache(maxsize=None)
 def trained_bank_multiscale(levels: int = 2, n_pairs: int = 8, size: int = 128, q_theta: int = 24,
-                            q_s: int = 3, q_c: int = 3, radius: int = 3, lam: float = 1e-3, sigma: float = 25.0):
+                            q_s: int = 3, q_c: int = 3, radius: int = 3, lam: float = 1e-3, sigma: float = 25.0,
+                            selector: str = "rgb"):
     """Oracle-trained multiscale bank (float64) on seeded synthetic RGB pairs."""
     pairs = []
     for i in range(n_pairs):
         z, u = synth.noisy_pair(1 + i, size, size, 3, sigma)
         pairs.append((z.astype(np.float64), u.astype(np.float64)))
-    bank, _, _ = O.train_multiscale(pairs, levels, q_theta, q_s, q_c, radius, radius, lam)
+    bank, _, _ = O.train_multiscale(pairs, levels, q_theta, q_s, q_c, radius, radius, lam, selector=selector)
     return bank
 
 
@@ -43,7 +44,8 @@ def gpu_level(lb: O.LevelBank, channels: int, coeff_dtype=None, device="cuda"):
     import paper_1802_06130_amd as M
     dt = coeff_dtype or torch.float32
     co = torch.tensor(np.ascontiguousarray(lb.coeffs), dtype=torch.float64).to(dt).to(device)
-    return M.Level(lb.q_theta, lb.t_s, lb.t_c, lb.radius_g, lb.radius_f, co, channels)
+    sel = M.SELECT_LUMA if lb.selector == "luma" else M.SELECT_RGB
+    return M.Level(lb.q_theta, lb.t_s, lb.t_c, lb.radius_g, lb.radius_f, co, channels, sel)
 
 
 def gpu_bank(bank: O.Bank, channels: int, coeff_dtype=None, device="cuda"):
@@ -56,7 +58,8 @@ def index_parity(s_gpu: np.ndarray, z_level: np.ndarray, lb: O.LevelBank):
 
     Returns (mismatch mask, number of mismatches, number of near-boundary pixels).
     """
-    s_ref, margin = O.select(np.asarray(z_level, np.float64), lb.q_theta, lb.t_s, lb.t_c, return_margin=True)
+    s_ref, margin = O.select(np.asarray(z_level, np.float64), lb.q_theta, lb.t_s, lb.t_c, return_margin=True,
+                             selector=lb.selector)
     mism = s_gpu.astype(np.int64) != s_ref
     near = margin < NEAR
     bad = mism & ~near

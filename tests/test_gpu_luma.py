@@ -1,0 +1,177 @@
+"""Luma-only filter selection (the survey's selector ablation; Section 3 and Fig. 2 compare the
+colour structure tensor of Eq. (6) with the luma-only analysis of earlier methods) on the GPU,
+through the C ABI, against the oracle.
+
+Bars as for the colour selector: bucket maps equal to the oracle's except at pixels whose
+features lie within 1e-6 of a bucket boundary; features to 1e-13 (strength) and 1e-9 (coherence);
+float32 cascades within 1e-4 of the oracle, float16 storage within 2e-3 of its float16-storage
+mode; the batched form bit-identical to the per-image form.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from mdn_testlib import (TOL_F16, TOL_F32, gpu_bank, gpu_level, index_parity, max_abs, propagate_mask,
+                         trained_bank_multiscale)
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev(a):
+    return _torch().from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _host(t):
+    _torch().cuda.synchronize()
+    return t.float().cpu().numpy().astype(np.float64)
+
+
+def _luma_level(q_theta, q_s, q_c, seed=3):
+    zs = [synth.noisy_pair(seed + i, 96, 96, 3, 25)[0].astype(np.float64) for i in range(3)]
+    f = [O.level_features(z, "luma") for z in zs]
+    t_s = O.thresholds_from_features(np.concatenate([x[0] for x in f]), q_s)
+    t_c = O.thresholds_from_features(np.concatenate([x[1] for x in f]), q_c)
+    K = q_theta * q_s * q_c
+    return O.LevelBank(q_theta, t_s, t_c, 3, 3, np.zeros((K, 3, 98)), "luma")
+
+
+@pytest.mark.parametrize("q", [(24, 3, 3), (10, 4, 2)])
+@pytest.mark.parametrize("H,W", [(1, 1), (7, 7), (17, 33), (130, 97), (768, 1024)])
+@pytest.mark.parametrize("dtype", [np.float32, np.float16])
+def test_select_parity_luma(q, H, W, dtype):
+    import paper_1802_06130_amd as M
+    print(f"select luma q={q} {H}x{W} {np.dtype(dtype).name}", flush=True)
+    lb = _luma_level(*q)
+    z, _ = synth.noisy_pair(80 + W, H, W, 3, 25, dtype=dtype)
+    s = M.select_filters(_dev(z), gpu_level(lb, 3)).cpu().numpy()
+    _, n_mis, n_near = index_parity(s, z.astype(np.float64), lb)
+    print(f"  mismatches={n_mis} near-boundary={n_near}")
+    # the colour selector with the same thresholds picks different buckets
+    lb_rgb = O.LevelBank(lb.q_theta, lb.t_s, lb.t_c, 3, 3, lb.coeffs)
+    if H * W > 1000:
+        s_rgb = M.select_filters(_dev(z), gpu_level(lb_rgb, 3)).cpu().numpy()
+        assert np.mean(s_rgb != s) > 0.1
+
+
+def test_luma_features_match_oracle():
+    import paper_1802_06130_amd as M
+    z, _ = synth.noisy_pair(8, 70, 90, 3, 25)
+    st, co = M.level_features(_dev(z), M.SELECT_LUMA)
+    a, b, c = O.structure_tensor(O.selector_image(z.astype(np.float64), "luma"))
+    _, s_o, c_o = O.eigen_features(a, b, c)
+    assert np.max(np.abs(st.cpu().numpy() - s_o)) < 1e-13
+    assert np.max(np.abs(co.cpu().numpy() - c_o)) < 1e-9
+
+
+def test_luma_misses_the_equal_luma_edge_on_the_gpu():
+    """Fig. 2 on the GPU: an edge between two colours of equal luma lands in the lowest strength bin
+    everywhere under the luma selector and in the highest one under the colour selector."""
+    import paper_1802_06130_amd as M
+    c1 = np.array([0.9, 0.3, 0.5])
+    y1 = O.KR * c1[0] + O.KG * c1[1] + O.KB * c1[2]
+    c2 = np.array([0.2, 0.6, 0.0])
+    c2[2] = (y1 - O.KR * c2[0] - O.KG * c2[1]) / O.KB
+    z = np.empty((3, 32, 64), np.float32)
+    z[:, :, :32] = c1[:, None, None]
+    z[:, :, 32:] = c2[:, None, None]
+    lv = O.LevelBank(8, np.array([0.01, 0.05]), np.array([0.3, 0.6]), 3, 3, np.zeros((72, 3, 98)), "luma")
+    s = M.select_filters(_dev(z), gpu_level(lv, 3)).cpu().numpy()
+    assert np.all(s // 3 % 3 == 0)
+    lv.selector = "rgb"
+    s = M.select_filters(_dev(z), gpu_level(lv, 3)).cpu().numpy()
+    assert s[16, 32] // 3 % 3 == 2
+
+
+def _cascade(img, bank, storage, storage_t, tol):
+    import paper_1802_06130_amd as M
+    C, L = img.shape[0], len(bank.levels)
+    gb = gpu_bank(bank, C)
+    out = _host(M.denoise(_dev(img), gb, storage=M.F32 if storage == np.float32 else M.F16))
+    ref = O.denoise(img, bank, storage=storage)
+    pyr_g = M.pyramid_build(_dev(img), L, storage=storage_t)
+    pyr_o = O.build_pyramid(img, L + 1, storage=storage)
+    mask = np.zeros(pyr_o[L - 1].shape[1:], bool)
+    for lev in range(L - 1, -1, -1):
+        zg = _dev(img) if lev == 0 else pyr_g[lev - 1]
+        s = M.select_filters(zg, gb.levels[lev]).cpu().numpy()
+        mism, _, _ = index_parity(s, pyr_o[lev], bank.levels[lev])
+        if lev < L - 1:
+            mask = propagate_mask(mask, mism.shape, bank.levels[lev].radius_f)
+        mask = mask | mism
+    err = max_abs(out, ref, mask)
+    print(f"  max-abs={err:.3g} excluded px={int(mask.sum())}")
+    assert err <= tol
+    return out
+
+
+@pytest.mark.parametrize("H,W", [(9, 13), (200, 328)])
+def test_denoise_luma_bank_f32(H, W):
+    print(f"denoise luma 3-level f32 {H}x{W}", flush=True)
+    bank = trained_bank_multiscale(levels=2, selector="luma")
+    z, u = synth.noisy_pair(2003, H, W, 3, 25)
+    out = _cascade(z, bank, np.float32, _torch().float32, TOL_F32)
+    if H * W > 10000:
+        assert O.psnr(out, u) > O.psnr(z, u) + 5
+
+
+def test_denoise_luma_bank_f16_column_walk():
+    """float16 storage and coefficients: the selection walk in luma mode feeds the filtering walk."""
+    import paper_1802_06130_amd as M
+    torch = _torch()
+    print("denoise luma 4-level f16", flush=True)
+    bank = trained_bank_multiscale(levels=3, selector="luma")
+    z, u = synth.noisy_pair(4009, 250, 330, 3, 25, dtype=np.float16)
+    gb = gpu_bank(bank, 3, coeff_dtype=torch.float16)
+    out = _host(M.denoise(_dev(z), gb, storage=M.F16))
+    ref16 = O.denoise(z, bank, storage=np.float16)
+    L = 3
+    pyr_g = M.pyramid_build(_dev(z), L, storage=torch.float16)
+    pyr_o = O.build_pyramid(z, L + 1, storage=np.float16)
+    mask = np.zeros(pyr_o[L - 1].shape[1:], bool)
+    for lev in range(L - 1, -1, -1):
+        zg = _dev(z) if lev == 0 else pyr_g[lev - 1]
+        s = M.select_filters(zg, gb.levels[lev]).cpu().numpy()
+        mism, _, _ = index_parity(s, pyr_o[lev], bank.levels[lev])
+        if lev < L - 1:
+            mask = propagate_mask(mask, mism.shape, bank.levels[lev].radius_f)
+        mask = mask | mism
+    err = max_abs(out, ref16, mask)
+    print(f"  max-abs vs fp16-mode oracle {err:.3g}")
+    assert err <= TOL_F16
+    # batched form over ragged images: bit-identical to the per-image form
+    zs = [_dev(synth.noisy_pair(4100 + i, h, w, 3, 25, dtype=np.float16)[0]) for i, (h, w) in
+          enumerate([(250, 330), (61, 97), (128, 40)])]
+    plan = M.Plan(gb, M.F16, max_images=8)
+    outs = plan.denoise_batch(zs)
+    torch.cuda.synchronize()
+    for zt, ob in zip(zs, outs):
+        op = M.denoise(zt, gb, storage=M.F16)
+        assert np.array_equal(ob.cpu().numpy(), op.cpu().numpy())
+    plan.close()
+
+
+def test_train_luma_end_to_end():
+    import paper_1802_06130_amd as M
+    print("train multiscale, luma selector", flush=True)
+    pairs = [synth.noisy_pair(90 + i, 96, 96, 3, 25) for i in range(3)]
+    p64 = [(z.astype(np.float64), u.astype(np.float64)) for z, u in pairs]
+    bank_o, _, _ = O.train_multiscale(p64, 2, 8, 3, 3, 3, 3, 1e-3, storage=np.float32, selector="luma")
+    bank_g, _, _ = M.train_multiscale([(_dev(z), _dev(u)) for z, u in pairs], 2, 8, 3, 3, 3, 3, 1e-3,
+                                      selector=M.SELECT_LUMA)
+    for lo, lg in zip(bank_o.levels, bank_g.levels):
+        assert np.max(np.abs(lo.t_s - lg.t_s)) < 1e-12 and np.max(np.abs(lo.t_c - lg.t_c)) < 1e-9
+        assert lg.selector == M.SELECT_LUMA
+    z, u = synth.noisy_pair(2004, 120, 160, 3, 25)
+    lvls = [O.LevelBank(8, lg.t_s, lg.t_c, 3, 3, lg.coeffs.double().cpu().numpy(), "luma") for lg in bank_g.levels]
+    out_g = O.denoise(z, O.Bank(lvls), storage=np.float32)
+    out_o = O.denoise(z, bank_o, storage=np.float32)
+    err = float(np.max(np.abs(out_g - out_o)))
+    print(f"  output max-abs (GPU-trained vs oracle-trained, oracle cascade) {err:.3g}")
+    assert err < 1e-3
