@@ -34,6 +34,7 @@ __all__ = [
     "accumulate_level", "solve_level", "train_single", "train_multiscale",
     "CrossGramStats", "accumulate_level_cross", "solve_level_cross", "apply_level_cross",
     "psnr", "round_storage", "dihedral", "augment_pairs", "luma", "selector_image",
+    "down2_noise_gain", "pyramid_noise_gain", "paper_setup",
 ]
 
 # --------------------------------------------------------------------------------------
@@ -693,6 +694,47 @@ def train_multiscale(pairs, n_trained_levels: int, q_theta: int, q_s: int, q_c: 
         uhat = [round_storage(apply_level(to_filter_space(pz[i][lev]), smaps[i], lb, uhat[i]), storage)
                 for i in range(len(pairs))]
     return Bank(levels), stats_all, fallbacks
+
+
+# --------------------------------------------------------------------------------------
+# The paper's experimental configuration (Section 5): 16 orientation x 16 strength x 16
+# coherence buckets at every level; 5x5 filters at the finer level and 3x3 at the coarser one
+# for sigma < 10, 7x7 and 5x5 otherwise; as many levels as make the coarsest level's noise
+# standard deviation fall below 2 (in 8-bit units).
+# Readings: "finer level" is the level's own input (the g taps, Eq. (10)) and "coarser level"
+# the upsampled coarser output (the f taps); the noise of level l is the standard deviation of
+# the pyramid of white noise of standard deviation sigma at level l. Through the first down2 the
+# white noise keeps only 0.4044 of its deviation (R12); the output is no longer white, so the
+# deviation of later levels follows from the whole cascade, not from that factor alone.
+# --------------------------------------------------------------------------------------
+
+def down2_noise_gain() -> float:
+    """Standard deviation of down2 applied to unit white noise: the 2-D filter's root sum of
+    squared weights, i.e. the 1-D sum of squared weights (about 0.4044, R12)."""
+    w = down2_weights()
+    return float(np.sum(w * w))
+
+
+def pyramid_noise_gain(level: int) -> float:
+    """Standard deviation at pyramid level `level` of unit white noise at level 0 (away from the
+    borders): the root sum of squares of the cascade's weights on the level-0 samples, per axis,
+    squared for the separable 2-D cascade."""
+    n = 64 * 2 ** level
+    rows = np.eye(n)
+    for _ in range(level):
+        rows = _down2_axis(rows, 0)          # row j: weights of output sample j on the inputs
+    r = rows[rows.shape[0] // 2]
+    return float(np.sum(r * r))
+
+
+def paper_setup(sigma_8bit: float):
+    """(trained levels L, radius_f, radius_g, (q_theta, q_s, q_c)) for noise sigma (8-bit units);
+    the pyramid has L + 1 levels and the noise of its coarsest one is below 2."""
+    L = 1
+    while sigma_8bit * pyramid_noise_gain(L) >= 2.0:
+        L += 1
+    rf, rg = (1, 2) if sigma_8bit < 10 else (2, 3)
+    return L, rf, rg, (16, 16, 16)
 
 
 def psnr(est: np.ndarray, ref: np.ndarray) -> float:

@@ -633,3 +633,35 @@ def test_luma_misses_an_equal_luma_colour_edge():
     q = O.select(z, 8, t_s, t_c, selector="luma") // 3 % 3   # strength bin
     assert np.all(q == 0)
     assert O.select(z, 8, t_s, t_c)[8, 8] // 3 % 3 == 2
+
+
+# ----------------------------------------------------------------------------- the paper's configuration (Section 5)
+
+def test_down2_noise_gain_closed_form_and_measured():
+    w = O.down2_weights()
+    assert abs(O.down2_noise_gain() - float(np.sum(w * w))) == 0.0
+    assert abs(O.down2_noise_gain() - 424064 / 1024 ** 2) < 1e-15      # 2 (12^2 + 36^2 + 116^2 + 444^2) / 1024^2
+    rng = np.random.default_rng(21)
+    x = rng.standard_normal((1, 1024, 1024))
+    y = O.down2(x)[:, 8:-8, 8:-8]
+    assert abs(float(np.std(y)) - O.down2_noise_gain()) < 5e-3
+
+
+def test_pyramid_noise_gain_against_white_noise():
+    """The cascade's noise deviation per level: level 1 is the white-noise gain exactly; deeper
+    levels match the deviation measured on a pyramid of white noise (within sampling error)."""
+    assert abs(O.pyramid_noise_gain(1) - O.down2_noise_gain()) < 1e-15
+    rng = np.random.default_rng(22)
+    pyr = O.build_pyramid(rng.standard_normal((1, 1024, 1024)), 5)
+    for lev in range(1, 5):
+        m = 8
+        measured = float(np.std(pyr[lev][:, m:-m, m:-m]))
+        assert abs(measured / O.pyramid_noise_gain(lev) - 1) < 0.03, (lev, measured, O.pyramid_noise_gain(lev))
+    assert O.pyramid_noise_gain(2) > O.down2_noise_gain() ** 2      # correlated after the first level
+
+
+@pytest.mark.parametrize("sigma,want", [(5, (2, 1, 2)), (15, (3, 2, 3)), (25, (4, 2, 3)), (50, (5, 2, 3))])
+def test_paper_setup_levels_and_footprints(sigma, want):
+    L, rf, rg, q = O.paper_setup(sigma)
+    assert (L, rf, rg) == want and q == (16, 16, 16)
+    assert sigma * O.pyramid_noise_gain(L) < 2.0 <= sigma * O.pyramid_noise_gain(L - 1)
