@@ -36,7 +36,7 @@ typedef enum {
     MDN_EINVAL = 1,   /* bad argument: null pointer, size mismatch, unknown enum */
     MDN_ENOMEM = 2,   /* workspace too small */
     MDN_EDEVICE = 3,  /* HIP launch or runtime error */
-    MDN_ENOTSUP = 4,  /* valid but unsupported configuration (filter radius, K > 255, ...) */
+    MDN_ENOTSUP = 4,  /* valid but unsupported configuration (filter radius, K > 65536, ...) */
     MDN_ETIMEOUT = 5, /* serving: the request waited longer than the queue time-out */
     MDN_ECANCELED = 6 /* serving: the request was cancelled */
 } mdn_status;
@@ -120,8 +120,9 @@ mdn_status mdn_pyramid_build(const mdn_image* level0, int32_t n_out, const mdn_i
 mdn_status mdn_dihedral(const mdn_image* in, int32_t transform, const mdn_image* out, void* stream);
 
 /* Filter selector s(i) (Section 3, "Filter selection"; Eq. (6); features as in mdn_level).
- * z: RGB or grey image of the level. s_out: device uint8 [height][s_pitch]. */
-mdn_status mdn_select_filters(const mdn_image* z, const mdn_level* lvl, uint8_t* s_out,
+ * z: RGB or grey image of the level. s_out: device [height][s_pitch] selector map, uint8 when
+ * K <= 256 and uint16 when K > 256 (the paper's 16 x 16 x 16 buckets, Section 5). */
+mdn_status mdn_select_filters(const mdn_image* z, const mdn_level* lvl, void* s_out,
                               int64_t s_pitch, void* stream);
 
 /* One filtering step (Eq. (1) or Eq. (9)).
@@ -129,14 +130,15 @@ mdn_status mdn_select_filters(const mdn_image* z, const mdn_level* lvl, uint8_t*
  *           filtering, the selector reads RGB).
  * u_coarse: the coarser level's output (YCbCr, or RGB for the coarsest pyramid level, which
  *           is converted), size ceil(w/2) x ceil(h/2); NULL iff lvl->radius_f < 0.
- * s:        precomputed selector (device uint8 [height][s_pitch]) or NULL to select inline.
+ * s:        precomputed selector (device [height][s_pitch], uint8 or uint16 as for
+ *           mdn_select_filters) or NULL to select inline.
  * u_out:    output, YCbCr (intermediate levels) or RGB (converted back), or grey.
- * s_out:    NULL, or device uint8 [height][s_pitch] that receives the selector used (inline mode).
+ * s_out:    NULL, or a device map like s that receives the selector used (inline mode).
  * Float16 coefficients of 7x7/7x7 colour levels run the column-walk kernel in float16 arithmetic
  * with float32 accumulation; float32 coefficients keep float32 arithmetic throughout. */
-mdn_status mdn_apply_level(const mdn_image* z, const mdn_image* u_coarse, const uint8_t* s,
+mdn_status mdn_apply_level(const mdn_image* z, const mdn_image* u_coarse, const void* s,
                            int64_t s_pitch, const mdn_level* lvl, const mdn_image* u_out,
-                           uint8_t* s_out, void* stream);
+                           void* s_out, void* stream);
 
 /* Bytes of device workspace mdn_denoise needs for a width x height image with `channels`
  * channels, a bank of `levels` trained levels and pyramid storage dtype `storage`. */
@@ -173,7 +175,7 @@ typedef enum { MDN_GRAM_F32 = 0, MDN_GRAM_BF16X3 = 1 } mdn_gram_precision;
  * G [systems][D][D], b [systems][nrhs][D], yy [systems][nrhs], n [K] (samples per bucket).
  * System index: k*channels + c (per channel) or k (cross channel). Sizes: mdn_gram_dims. */
 typedef struct {
-    int32_t  K;          /* buckets (<= 255) */
+    int32_t  K;          /* buckets (<= 65536) */
     int32_t  channels;   /* 1 or 3 */
     int32_t  layout;     /* mdn_x_layout */
     int32_t  radius_f;   /* -1 (single scale) or 1..3; must be -1 for the cross layout */

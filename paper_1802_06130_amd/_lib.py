@@ -194,12 +194,24 @@ def augment_pairs(pairs):
     return [(dihedral(z, t), dihedral(u, t)) for z, u in pairs for t in range(8)]
 
 
+def selector_dtype(level: Level):
+    """Element type of a level's selector maps: uint8 for K <= 256 buckets, uint16 above."""
+    torch = _torch()
+    return torch.uint16 if level.K > 256 else torch.uint8
+
+
+def _check_map(t, level: Level, name: str):
+    if t is not None and t.dtype != selector_dtype(level):
+        raise MdnError(MDN_EINVAL, f"{name}: selector maps of a {level.K}-bucket level are {selector_dtype(level)}")
+
+
 def select_filters(z, level: Level, out=None):
-    """uint8 (H, W) bucket map of the RGB/grey image z."""
+    """(H, W) bucket map of the RGB/grey image z (uint8, or uint16 when K > 256)."""
     torch = _torch()
     C, H, W = z.shape
     if out is None:
-        out = torch.empty((H, W), dtype=torch.uint8, device=z.device)
+        out = torch.empty((H, W), dtype=selector_dtype(level), device=z.device)
+    _check_map(out, level, "out")
     lv = level.desc()
     _check(lib().mdn_select_filters(ct.byref(image(z)), ct.byref(lv), ct.c_void_p(out.data_ptr()),
                                     out.stride(0) if H > 0 else W, _stream_ptr()))
@@ -209,7 +221,8 @@ def select_filters(z, level: Level, out=None):
 def apply_level(z, level: Level, u_coarse=None, s=None, out=None, out_color=None, coarse_color=None,
                 out_dtype=None, s_out=None):
     """One filtering step; returns u_out (C, H, W) in YCbCr unless out_color says otherwise.
-    ``s_out`` (uint8 (H, W) tensor) receives the selector used when selecting inline."""
+    ``s_out`` ((H, W) map, uint8 or uint16 as for select_filters) receives the selector used when
+    selecting inline."""
     torch = _torch()
     C, H, W = z.shape
     if out_color is None:
@@ -221,7 +234,9 @@ def apply_level(z, level: Level, u_coarse=None, s=None, out=None, out_color=None
         uc = image(u_coarse, coarse_color if coarse_color is not None else (GRAY if C == 1 else YCC))
     lv = level.desc()
     if s is None and s_out is None and u_coarse is not None and level.coeffs.dtype == torch.float16 and C == 3:
-        s_out = torch.empty((H, W), dtype=torch.uint8, device=z.device)   # the float16 path's selector map
+        s_out = torch.empty((H, W), dtype=selector_dtype(level), device=z.device)   # the float16 path's map
+    _check_map(s, level, "s")
+    _check_map(s_out, level, "s_out")
     sp = s.stride(0) if s is not None else (s_out.stride(0) if s_out is not None else 0)
     _check(lib().mdn_apply_level(ct.byref(image(z)), ct.byref(uc) if uc is not None else None,
                                  ct.c_void_p(s.data_ptr()) if s is not None else None, sp, ct.byref(lv),

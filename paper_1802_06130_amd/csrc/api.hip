@@ -70,7 +70,7 @@ mdn_status check_level(const mdn_level* lv, int channels) {
     if (lv->q_s < 1 || lv->q_s > kMaxThr || lv->q_c < 1 || lv->q_c > kMaxThr)
         return fail(MDN_EINVAL, "level: q_s and q_c must be in [1, %d]", kMaxThr);
     const int K = lv->q_theta * lv->q_s * lv->q_c;
-    if (K > 255) return fail(MDN_ENOTSUP, "level: K = %d > 255 buckets is not supported (uint8 selector)", K);
+    if (K > 65536) return fail(MDN_ENOTSUP, "level: K = %d > 65536 buckets is not supported (uint16 selector)", K);
     if (lv->channels != channels) return fail(MDN_EINVAL, "level: channels %d != image channels %d", lv->channels, channels);
     if (lv->coeff_dtype != MDN_F32 && lv->coeff_dtype != MDN_F16) return fail(MDN_EINVAL, "level: unknown coeff dtype");
     if (lv->radius_g < 1 || lv->radius_g > 3) return fail(MDN_ENOTSUP, "level: radius_g must be 1..3");
@@ -114,7 +114,7 @@ size_t image_bytes(int w, int h, int c, int dtype) {
 mdn_status check_gram(const mdn_gram* g) {
     if (!g) return fail(MDN_EINVAL, "gram: null");
     if (g->reserved != 0) return fail(MDN_EINVAL, "gram: reserved field must be 0");
-    if (g->K < 1 || g->K > 255) return fail(MDN_EINVAL, "gram: K must be 1..255");
+    if (g->K < 1 || g->K > 65536) return fail(MDN_EINVAL, "gram: K must be 1..65536");
     if (g->channels != 1 && g->channels != 3) return fail(MDN_EINVAL, "gram: channels must be 1 or 3");
     if (g->layout != MDN_X_PER_CHANNEL && g->layout != MDN_X_CROSS_CHANNEL) return fail(MDN_EINVAL, "gram: layout");
     if (g->radius_g < 1 || g->radius_g > 3) return fail(MDN_ENOTSUP, "gram: radius_g must be 1..3");
@@ -182,7 +182,7 @@ mdn_status mdn_dihedral(const mdn_image* in, int32_t transform, const mdn_image*
     return launch_dihedral(*in, *out, transform, static_cast<hipStream_t>(stream));
 }
 
-mdn_status mdn_select_filters(const mdn_image* z, const mdn_level* lvl, uint8_t* s_out, int64_t s_pitch,
+mdn_status mdn_select_filters(const mdn_image* z, const mdn_level* lvl, void* s_out, int64_t s_pitch,
                               void* stream) {
     g_err[0] = 0;
     mdn_status st = check_image(z, "z");
@@ -195,8 +195,8 @@ mdn_status mdn_select_filters(const mdn_image* z, const mdn_level* lvl, uint8_t*
     return launch_select_apply(*z, nullptr, nullptr, s_pitch, s_out, *lvl, nullptr, static_cast<hipStream_t>(stream));
 }
 
-mdn_status mdn_apply_level(const mdn_image* z, const mdn_image* u_coarse, const uint8_t* s, int64_t s_pitch,
-                           const mdn_level* lvl, const mdn_image* u_out, uint8_t* s_out, void* stream) {
+mdn_status mdn_apply_level(const mdn_image* z, const mdn_image* u_coarse, const void* s, int64_t s_pitch,
+                           const mdn_level* lvl, const mdn_image* u_out, void* s_out, void* stream) {
     g_err[0] = 0;
     mdn_status st = check_image(z, "z");
     if (st) return st;

@@ -38,9 +38,10 @@ struct FilterArgs {
     int32_t z_dtype;
     ImageArg uc;                // coarser output (may be empty)
     int32_t uc_dtype, uc_rgb;
-    const uint8_t* s_in;        // precomputed selector or null
+    const void* s_in;           // precomputed selector or null
     int64_t s_pitch;
-    uint8_t* s_out;             // selector output or null
+    void* s_out;                // selector output or null
+    int32_t s16;                // selector maps hold uint16 (K > 256) instead of uint8
     void* out;
     int64_t out_row, out_plane;
     int32_t out_dtype, out_rgb;
@@ -228,14 +229,21 @@ __global__ __launch_bounds__(256) void k_select_apply(FilterArgs a) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int y = y0 + ty + 4 * k, x = x0 + tx;
-            sv[k] = (y < H && x < W) ? (int)a.s_in[(int64_t)y * a.s_pitch + x] : 0;
+            const int64_t o = (int64_t)y * a.s_pitch + x;
+            sv[k] = (y < H && x < W) ? (a.s16 ? (int)static_cast<const uint16_t*>(a.s_in)[o]
+                                              : (int)static_cast<const uint8_t*>(a.s_in)[o])
+                                     : 0;
         }
     }
     if (a.s_out != nullptr) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int y = y0 + ty + 4 * k, x = x0 + tx;
-            if (y < H && x < W) a.s_out[(int64_t)y * a.s_pitch + x] = (uint8_t)sv[k];
+            const int64_t o = (int64_t)y * a.s_pitch + x;
+            if (y < H && x < W) {
+                if (a.s16) static_cast<uint16_t*>(a.s_out)[o] = (uint16_t)sv[k];
+                else static_cast<uint8_t*>(a.s_out)[o] = (uint8_t)sv[k];
+            }
         }
     }
     if constexpr (!APPLY) return;
@@ -394,15 +402,15 @@ void orientation_boundaries(int q_theta, double* bcos, double* bsin) {
     }
 }
 
-mdn_status launch_select_apply(const mdn_image& z, const mdn_image* uc, const uint8_t* s_in, int64_t s_pitch,
-                               uint8_t* s_out, const mdn_level& lvl, const mdn_image* out, hipStream_t st) {
+mdn_status launch_select_apply(const mdn_image& z, const mdn_image* uc, const void* s_in, int64_t s_pitch,
+                               void* s_out, const mdn_level& lvl, const mdn_image* out, hipStream_t st) {
     if (z.width == 0 || z.height == 0) return MDN_OK;
     // selector only: column-walk float64 selection pass
     if (!out && s_out && !s_in) return launch_select_walk(z, lvl, s_out, s_pitch, st);
     // float16 filter banks of 7x7/7x7 colour filters run on the persistent column-walk kernel
     if (out && uc && lvl.coeff_dtype == MDN_F16 && walk_supported(lvl, z.channels)) {
         if (!s_in && !s_out) return fail(MDN_EINVAL, "float16 levels need a selector map (s) or a buffer for it (s_out)");
-        return launch_walk(z, *uc, lvl, *out, s_in, s_out, s_pitch, st);
+        return launch_walk(z, *uc, lvl, *out, static_cast<const uint8_t*>(s_in), static_cast<uint8_t*>(s_out), s_pitch, st);
     }
     FilterArgs fa;
     memset(&fa, 0, sizeof(fa));
@@ -414,6 +422,7 @@ mdn_status launch_select_apply(const mdn_image& z, const mdn_image* uc, const ui
         fa.uc_rgb = uc->color == MDN_RGB;
     }
     fa.s_in = s_in;
+    fa.s16 = wide_selector(lvl);
     fa.s_pitch = s_pitch;
     fa.s_out = s_out;
     if (out) {

@@ -100,14 +100,16 @@ mdn_status launch_down2_walk(const mdn_image& in, const mdn_image& out, hipStrea
 inline mdn_status launch_down2(const mdn_image& in, const mdn_image& out, hipStream_t st) {
     return launch_down2_walk(in, out, st);
 }
-mdn_status launch_select_apply(const mdn_image& z, const mdn_image* uc, const uint8_t* s_in,
-                               int64_t s_pitch, uint8_t* s_out, const mdn_level& lvl,
+// Selector maps hold uint8 when K <= 256 and uint16 otherwise (s_pitch in elements).
+inline bool wide_selector(const mdn_level& lvl) { return lvl.q_theta * lvl.q_s * lvl.q_c > 256; }
+mdn_status launch_select_apply(const mdn_image& z, const mdn_image* uc, const void* s_in,
+                               int64_t s_pitch, void* s_out, const mdn_level& lvl,
                                const mdn_image* out, hipStream_t st);
 
 bool walk_supported(const mdn_level& lvl, int channels);
 mdn_status launch_walk(const mdn_image& z, const mdn_image& uc, const mdn_level& lvl, const mdn_image& out,
                        const uint8_t* s_in, uint8_t* s_buf, int64_t s_pitch, hipStream_t st);
-mdn_status launch_select_walk(const mdn_image& z, const mdn_level& lvl, uint8_t* s, int64_t s_pitch, hipStream_t st);
+mdn_status launch_select_walk(const mdn_image& z, const mdn_level& lvl, void* s, int64_t s_pitch, hipStream_t st);
 mdn_status launch_dihedral(const mdn_image& in, const mdn_image& out, int t, hipStream_t st);
 mdn_status launch_features(const mdn_image& z, int luma, double* strength, double* coherence, hipStream_t st);
 

@@ -139,7 +139,7 @@ __device__ __forceinline__ int bucket(double a, double b, double c, const SelWal
     return (qt * q_s + qs) * q_c + qc;
 }
 
-template <typename TZ, int C, bool LUMA, int QS, int QC, int MQ, int NSTEP>
+template <typename TZ, typename TS, int C, bool LUMA, int QS, int QC, int MQ, int NSTEP>
 __global__ __launch_bounds__(64 * kWaves, MDN_SEL_WAVES_PER_SIMD) void k_select_walk(SelWalkArgs a) {
     static_assert(!LUMA || C == 3, "the luma selector reads RGB");
     constexpr int NC = LUMA ? 1 : C;                             // channels of the selector image
@@ -267,7 +267,7 @@ __global__ __launch_bounds__(64 * kWaves, MDN_SEL_WAVES_PER_SIMD) void k_select_
                 const double sb = (((hr[0].B + hr[1].B) + hr[2].B) + hr[3].B) + hr[4].B;
                 const double sc = (((hr[0].C + hr[1].C) + hr[2].C) + hr[3].C) + hr[4].C;
                 const int s = bucket<QS, QC, MQ, NSTEP>(sa, sb, sc, a, bt);
-                if (out_lane && y < ye) *((MDN_GLOBAL uint8_t*)im.s + (uint32_t)y * (uint32_t)im.s_pitch + (uint32_t)x) = (uint8_t)s;
+                if (out_lane && y < ye) *((MDN_GLOBAL TS*)im.s + (uint32_t)y * (uint32_t)im.s_pitch + (uint32_t)x) = (TS)s;
             }, std::make_integer_sequence<int, 10>{});
         }
     }
@@ -312,11 +312,13 @@ mdn_status launch_select_args(const SelWalkArgs& a, int channels, int z_dtype, h
     const int grid = blocks < 8 * ncu ? blocks : 8 * ncu;
     // 3 x 3 strength/coherence bins with 24 or 16 orientation bins get fixed-count instances
     const int spec = (a.q_s == 3 && a.q_c == 3) ? (a.q_theta == 24 ? 1 : a.q_theta == 16 ? 2 : 0) : 0;
+    const bool wide = a.q_theta * a.q_s * a.q_c > 256;      // uint16 selector map
 #define MDN_SEL_LAUNCH(TZ_, C_, L_)                                                                 \
     do {                                                                                               \
-        if (spec == 1) k_select_walk<TZ_, C_, L_, 3, 3, 5, 0><<<grid, 64 * kWaves, 0, st>>>(a);         \
-        else if (spec == 2) k_select_walk<TZ_, C_, L_, 3, 3, 3, 0><<<grid, 64 * kWaves, 0, st>>>(a);    \
-        else k_select_walk<TZ_, C_, L_, 0, 0, 0, 5><<<grid, 64 * kWaves, 0, st>>>(a);                   \
+        if (spec == 1) k_select_walk<TZ_, uint8_t, C_, L_, 3, 3, 5, 0><<<grid, 64 * kWaves, 0, st>>>(a);         \
+        else if (spec == 2) k_select_walk<TZ_, uint8_t, C_, L_, 3, 3, 3, 0><<<grid, 64 * kWaves, 0, st>>>(a);    \
+        else if (wide) k_select_walk<TZ_, uint16_t, C_, L_, 0, 0, 0, 5><<<grid, 64 * kWaves, 0, st>>>(a);        \
+        else k_select_walk<TZ_, uint8_t, C_, L_, 0, 0, 0, 5><<<grid, 64 * kWaves, 0, st>>>(a);                   \
     } while (0)
     if (channels == 3 && a.luma) {
         if (z_dtype == MDN_F16) MDN_SEL_LAUNCH(_Float16, 3, true);
@@ -332,7 +334,7 @@ mdn_status launch_select_args(const SelWalkArgs& a, int channels, int z_dtype, h
     return check_launch("select_walk");
 }
 
-mdn_status launch_select_walk(const mdn_image& z, const mdn_level& lvl, uint8_t* s, int64_t s_pitch, hipStream_t st) {
+mdn_status launch_select_walk(const mdn_image& z, const mdn_level& lvl, void* s, int64_t s_pitch, hipStream_t st) {
     if (z.width == 0 || z.height == 0) return MDN_OK;
     SelWalkArgs a;
     memset(&a, 0, sizeof(a));

@@ -55,9 +55,12 @@ __host__ __device__ inline int seg_chunks(int chunks, int nseg) {
 // columns) fall in 64 distinct banks.
 template <int PREC> struct Ldw { static constexpr int v = PREC == 0 ? kChunk + 2 : kChunk + 8; };
 
-int gram_segments(int64_t npx) {
+// Segments per bucket: enough to spread a big bucket over several workgroups, fewer when the
+// buckets are many (and so small on average), which also bounds the partial-sum buffer.
+int gram_segments(int64_t npx, int K) {
     const int64_t s = (npx + 16383) / 16384;
-    return (int)(s < 1 ? 1 : (s > kMaxSeg ? kMaxSeg : s));
+    const int cap = K <= 256 ? kMaxSeg : (kMaxSeg * 256 / K > 1 ? kMaxSeg * 256 / K : 1);
+    return (int)(s < 1 ? 1 : (s > cap ? cap : s));
 }
 
 // feature descriptor: source (0 fine, 1 coarse, 2 target), plane, dy, dx
@@ -322,7 +325,8 @@ __global__ void k_iota(int32_t* p, int64_t n) {
 }
 
 // off[k] = first position of a key >= k in the sorted keys, k = 0..K
-__global__ void k_bucket_bounds(const uint8_t* keys, int64_t n, int K, int32_t* off) {
+template <typename TK>
+__global__ void k_bucket_bounds(const TK* keys, int64_t n, int K, int32_t* off) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k > K) return;
     int64_t lo = 0, hi = n;
@@ -527,10 +531,14 @@ mdn_status gram_zero(const mdn_gram& g, hipStream_t st) {
     return check_launch("gram_zero");
 }
 
-static size_t sort_tmp_bytes(int64_t n) {
+static size_t sort_tmp_bytes(int64_t n, bool wide) {
     size_t tmp = 0;
-    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, (const uint8_t*)nullptr, (uint8_t*)nullptr,
-                                             (const int32_t*)nullptr, (int32_t*)nullptr, (int)n, 0, 8);
+    if (wide)
+        (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, (const uint16_t*)nullptr, (uint16_t*)nullptr,
+                                                 (const int32_t*)nullptr, (int32_t*)nullptr, (int)n, 0, 16);
+    else
+        (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tmp, (const uint8_t*)nullptr, (uint8_t*)nullptr,
+                                                 (const int32_t*)nullptr, (int32_t*)nullptr, (int)n, 0, 8);
     return tmp;
 }
 
@@ -548,9 +556,9 @@ size_t train_ws_bytes(const mdn_gram& g, int w, int h) {
     const int C = g.channels;
     const int wc = (w + 1) / 2, hc = (h + 1) / 2;
     const size_t n = (size_t)w * h;
-    const size_t part = (size_t)g.K * spk * gram_segments((int64_t)n) * gram_tiles(g) * 1024 * 4;
-    return al(n * C * 4) * 2 + al((size_t)wc * hc * C * 4) + al(n) * 2 + al(n * 4) * 2 + al(257 * 4) +
-           al(sort_tmp_bytes((int64_t)n)) + al(part);
+    const size_t part = (size_t)g.K * spk * gram_segments((int64_t)n, g.K) * gram_tiles(g) * 1024 * 4;
+    return al(n * C * 4) * 2 + al((size_t)wc * hc * C * 4) + al(n * 2) * 2 + al(n * 4) * 2 +
+           al(((size_t)g.K + 1) * 4) + al(sort_tmp_bytes((int64_t)n, g.K > 256)) + al(part);
 }
 
 mdn_status launch_to_planes(const mdn_image& im, float* out, int64_t row, int64_t plane, hipStream_t st) {
@@ -574,18 +582,20 @@ mdn_status train_accumulate(const mdn_gram& g, const mdn_image& z, const mdn_ima
     p += al((size_t)W * H * C * 4);
     float* coarse = reinterpret_cast<float*>(p);
     p += al((size_t)Wc * Hc * C * 4);
-    uint8_t* smap = reinterpret_cast<uint8_t*>(p);
-    p += al((size_t)W * H);
-    uint8_t* skeys = reinterpret_cast<uint8_t*>(p);
-    p += al((size_t)W * H);
+    // selector map and sorted keys: uint8, or uint16 when K > 256
+    const bool wide = g.K > 256;
+    void* smap = p;
+    p += al((size_t)W * H * 2);
+    void* skeys = p;
+    p += al((size_t)W * H * 2);
     int32_t* idx_in = reinterpret_cast<int32_t*>(p);
     p += al((size_t)W * H * 4);
     int32_t* idx = reinterpret_cast<int32_t*>(p);
     p += al((size_t)W * H * 4);
     int32_t* off = reinterpret_cast<int32_t*>(p);
-    p += al(257 * 4);
+    p += al(((size_t)g.K + 1) * 4);
     void* sort_tmp = p;
-    p += al(sort_tmp_bytes((int64_t)W * H));
+    p += al(sort_tmp_bytes((int64_t)W * H, wide));
     float* part = reinterpret_cast<float*>(p);
     mdn_status s;
     if ((s = launch_to_planes(z, fine, W, (int64_t)W * H, st))) return s;
@@ -595,10 +605,15 @@ mdn_status train_accumulate(const mdn_gram& g, const mdn_image& z, const mdn_ima
     const int64_t npx = (int64_t)W * H;
     k_iota<<<256, 256, 0, st>>>(idx_in, npx);
     if ((s = check_launch("iota"))) return s;
-    size_t tmp = sort_tmp_bytes(npx);
-    if (hipcub::DeviceRadixSort::SortPairs(sort_tmp, tmp, smap, skeys, idx_in, idx, (int)npx, 0, 8, st) != hipSuccess)
-        return fail(MDN_EDEVICE, "gram: bucket sort failed");
-    k_bucket_bounds<<<(g.K + 1 + 255) / 256, 256, 0, st>>>(skeys, npx, g.K, off);
+    size_t tmp = sort_tmp_bytes(npx, wide);
+    const hipError_t se =
+        wide ? hipcub::DeviceRadixSort::SortPairs(sort_tmp, tmp, static_cast<const uint16_t*>(smap), static_cast<uint16_t*>(skeys),
+                                                  idx_in, idx, (int)npx, 0, 16, st)
+             : hipcub::DeviceRadixSort::SortPairs(sort_tmp, tmp, static_cast<const uint8_t*>(smap), static_cast<uint8_t*>(skeys),
+                                                  idx_in, idx, (int)npx, 0, 8, st);
+    if (se != hipSuccess) return fail(MDN_EDEVICE, "gram: bucket sort failed");
+    if (wide) k_bucket_bounds<<<(g.K + 1 + 255) / 256, 256, 0, st>>>(static_cast<const uint16_t*>(skeys), npx, g.K, off);
+    else k_bucket_bounds<<<(g.K + 1 + 255) / 256, 256, 0, st>>>(static_cast<const uint8_t*>(skeys), npx, g.K, off);
     if ((s = check_launch("bucket_bounds"))) return s;
 
     GramArgs a;
@@ -634,7 +649,7 @@ mdn_status train_accumulate(const mdn_gram& g, const mdn_image& z, const mdn_ima
         for (int c = 0; c < C; ++c) a.feat[f++] = feat_pack(2, c, 0, 0);
     }
     a.Daug = f;
-    a.nseg = gram_segments((int64_t)W * H);
+    a.nseg = gram_segments((int64_t)W * H, g.K);
     a.part = part;
     a.G = g.G;
     a.b = g.b;

@@ -40,7 +40,7 @@ struct WalkArgs {
 
 struct SelImage {
     const void* z;
-    uint8_t* s;
+    void* s;                    // selector map: uint8, or uint16 when K > 256
     int64_t z_row, z_plane, s_pitch;
     int32_t W, H, C;
     int32_t nsx, strip_begin, rows;     // strips across, first strip, rows per strip (multiple of 10)

@@ -65,7 +65,7 @@ def _level(**kw):
     (_img(data=0x1000, dtype=7), _level(), "dtype"),
     (_img(data=0x1000, reserved=1), _level(), "reserved"),
     (_img(data=0x1000), _level(q_theta=23), "q_theta"),
-    (_img(data=0x1000), _level(q_theta=64, q_s=3, q_c=3), "255"),
+    (_img(data=0x1000), _level(q_theta=64, q_s=17, q_c=3), "q_s"),
     (_img(data=0x1000), _level(radius_g=4), "radius_g"),
     (_img(data=0x1000), _level(channels=1), "channels"),
     (_img(data=0x1000), _level(coeffs=None), "coeffs"),

@@ -1,0 +1,170 @@
+"""The paper's experimental configuration (Section 5; the survey's NEXT-1) on the GPU, through the
+C ABI, against the oracle: 16 x 16 x 16 = 4096 buckets (uint16 selector maps), 7x7 denoise and 5x5
+upscale filters, pyramid depth from the noise level.
+
+Bars as everywhere: bucket maps equal the oracle's except at pixels within 1e-6 of a bucket
+boundary; float32 cascades within 1e-4 of the oracle excluding pixels downstream of such a flip;
+the normal equations' sample counts exact and G within 2e-5 sqrt(G_pp G_qq). The batched and
+served forms keep the bank in LDS and refuse such banks with MDN_ENOTSUP.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from mdn_testlib import TOL_F32, gpu_bank, gpu_level, index_parity, max_abs, propagate_mask
+
+pytestmark = pytest.mark.gpu
+
+Q = (16, 16, 16)
+K = 16 * 16 * 16
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev(a):
+    return _torch().from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _host(t):
+    _torch().cuda.synchronize()
+    return t.float().cpu().numpy().astype(np.float64)
+
+
+def _thresholds(zs):
+    f = [O.level_features(z.astype(np.float64)) for z in zs]
+    return (O.thresholds_from_features(np.concatenate([x[0] for x in f]), 16),
+            O.thresholds_from_features(np.concatenate([x[1] for x in f]), 16))
+
+
+def _bank(L, rf, rg, seed=5):
+    """Random (normalised) filters for inference plumbing; thresholds per level from the features of
+    seeded scenes at that level (equal-population quantiles)."""
+    zs = [synth.noisy_pair(300 + i, 160, 160, 3, 25)[0].astype(np.float64) for i in range(3)]
+    levels = []
+    for lev in range(L):
+        t_s, t_c = _thresholds([O.build_pyramid(z, lev + 1)[lev] for z in zs])
+        co = synth.random_bank_coeffs(seed + lev, K, 3, (2 * rf + 1) ** 2, (2 * rg + 1) ** 2)
+        levels.append(O.LevelBank(16, t_s, t_c, rg, rf, co))
+    return O.Bank(levels)
+
+
+@pytest.mark.parametrize("H,W", [(1, 1), (17, 33), (130, 97), (768, 1024)])
+@pytest.mark.parametrize("dtype", [np.float32, np.float16])
+def test_select_4096_buckets_uint16_map(H, W, dtype):
+    import paper_1802_06130_amd as M
+    torch = _torch()
+    print(f"select 4096 buckets {H}x{W} {np.dtype(dtype).name}", flush=True)
+    lb = _bank(1, 2, 3).levels[0]
+    z, _ = synth.noisy_pair(400 + W, H, W, 3, 25, dtype=dtype)
+    s = M.select_filters(_dev(z), gpu_level(lb, 3))
+    assert s.dtype == torch.uint16
+    sn = s.cpu().numpy()
+    _, n_mis, n_near = index_parity(sn, z.astype(np.float64), lb)
+    print(f"  mismatches={n_mis} near-boundary={n_near} buckets used={len(np.unique(sn))}")
+    if H * W > 100000:
+        assert len(np.unique(sn)) > 2000 and int(sn.max()) > 255
+
+
+def test_denoise_paper_configuration_f32():
+    """sigma = 25: five-level pyramid (four trained levels), 7x7 denoise / 5x5 upscale filters."""
+    import paper_1802_06130_amd as M
+    torch = _torch()
+    L, rf, rg, q = O.paper_setup(25)
+    assert (L, rf, rg, q) == (4, 2, 3, Q)
+    bank = _bank(L, rf, rg)
+    z, u = synth.noisy_pair(2010, 300, 412, 3, 25)
+    gb = gpu_bank(bank, 3)
+    out = _host(M.denoise(_dev(z), gb, storage=M.F32))
+    ref = O.denoise(z, bank, storage=np.float32)
+    pyr_g = M.pyramid_build(_dev(z), L, storage=torch.float32)
+    pyr_o = O.build_pyramid(z, L + 1, storage=np.float32)
+    mask = np.zeros(pyr_o[L - 1].shape[1:], bool)
+    for lev in range(L - 1, -1, -1):
+        zg = _dev(z) if lev == 0 else pyr_g[lev - 1]
+        s = M.select_filters(zg, gb.levels[lev]).cpu().numpy()
+        mism, _, _ = index_parity(s, pyr_o[lev], bank.levels[lev])
+        if lev < L - 1:
+            mask = propagate_mask(mask, mism.shape, rf)
+        mask = mask | mism
+    err = max_abs(out, ref, mask)
+    print(f"  max-abs={err:.3g} excluded px={int(mask.sum())}")
+    assert err <= TOL_F32
+
+
+def test_apply_with_precomputed_uint16_map_equals_inline():
+    import paper_1802_06130_amd as M
+    torch = _torch()
+    lb = _bank(1, 2, 3).levels[0]
+    z, _ = synth.noisy_pair(2011, 120, 150, 3, 25)
+    zc = M.pyramid_build(_dev(z), 1)[0]
+    lv = gpu_level(lb, 3)
+    s_out = torch.empty((120, 150), dtype=torch.uint16, device="cuda")
+    a = M.apply_level(_dev(z), lv, u_coarse=zc, coarse_color=M.RGB, s_out=s_out)
+    b = M.apply_level(_dev(z), lv, u_coarse=zc, coarse_color=M.RGB, s=M.select_filters(_dev(z), lv))
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    assert torch.equal(s_out, M.select_filters(_dev(z), lv))
+    with pytest.raises(M.MdnError):
+        M.apply_level(_dev(z), lv, u_coarse=zc, coarse_color=M.RGB, s=torch.zeros((120, 150), dtype=torch.uint8,
+                                                                                  device="cuda"))
+
+
+def test_normal_equations_4096_buckets():
+    import paper_1802_06130_amd as M
+    print("gram 4096 buckets, 7x7 + 5x5", flush=True)
+    pairs = [synth.noisy_pair(500 + i, 96, 112, 3, 25) for i in range(2)]
+    t_s, t_c = _thresholds([z for z, _ in pairs])
+    lb = O.LevelBank(16, t_s, t_c, 3, 2, np.zeros((K, 3, 74)))
+    sel = gpu_level(lb, 3)
+    g = M.Gram(K, 3, 3, 2)
+    st = O.GramStats.zeros(K, 3, 74)
+    for z, u in pairs:
+        z64, u64 = z.astype(np.float64), u.astype(np.float64)
+        zc = M.pyramid_build(_dev(z), 1)[0]
+        M.train_accumulate(g, _dev(z), _dev(u), sel, u_coarse=zc, coarse_color=M.RGB)
+        s = M.select_filters(_dev(z), sel).cpu().numpy().astype(np.int64)
+        index_parity(s, z64, lb)
+        pz = O.build_pyramid(z64, 2, storage=np.float32)
+        O.accumulate_level(st, s, O.to_filter_space(z64), O.to_filter_space(u64), 3, 2, O.to_filter_space(pz[1]))
+    assert np.array_equal(g.n.cpu().numpy(), st.n)
+    Gg = g.G.cpu().numpy().reshape(st.G.shape)
+    diag = np.sqrt(np.maximum(np.einsum("kcii->kci", st.G), 0.0))
+    bound = 2e-5 * diag[:, :, :, None] * diag[:, :, None, :] + 1e-12
+    worst = float((np.abs(Gg - st.G) / bound).max())
+    print(f"  buckets hit {int((st.n > 0).sum())}, worst |dG| / bound = {worst:.3g}")
+    assert worst <= 1.0
+
+
+def test_train_paper_configuration_end_to_end():
+    """sigma = 5: three-level pyramid, 5x5 denoise / 3x3 upscale filters, 4096 buckets (most fall back
+    to the pooled solution with this little data), trained on both sides."""
+    import paper_1802_06130_amd as M
+    L, rf, rg, (qt, qs, qc) = O.paper_setup(5)
+    assert (L, rf, rg) == (2, 1, 2)
+    pairs = [synth.noisy_pair(600 + i, 96, 96, 3, 5) for i in range(3)]
+    p64 = [(z.astype(np.float64), u.astype(np.float64)) for z, u in pairs]
+    bank_o, _, fb_o = O.train_multiscale(p64, L, qt, qs, qc, rf, rg, 1e-3, storage=np.float32)
+    bank_g, _, fb_g = M.train_multiscale([(_dev(z), _dev(u)) for z, u in pairs], L, qt, qs, qc, rf, rg, 1e-3)
+    for lo, lg in zip(bank_o.levels, bank_g.levels):
+        assert np.max(np.abs(lo.t_s - lg.t_s)) < 1e-12 and np.max(np.abs(lo.t_c - lg.t_c)) < 1e-9
+    z, u = synth.noisy_pair(2012, 120, 160, 3, 5)
+    lvls = [O.LevelBank(qt, lg.t_s, lg.t_c, rg, rf, lg.coeffs.double().cpu().numpy()) for lg in bank_g.levels]
+    out_g = O.denoise(z, O.Bank(lvls), storage=np.float32)
+    out_o = O.denoise(z, bank_o, storage=np.float32)
+    err = float(np.max(np.abs(out_g - out_o)))
+    print(f"  fallback systems GPU {fb_g} oracle {[3 * int(f.sum()) for f in fb_o]}; output max-abs {err:.3g}; "
+          f"PSNR {O.psnr(z, u):.2f} -> {O.psnr(out_g, u):.2f} dB")
+    assert err < 1e-3
+
+
+def test_batched_form_refuses_4096_buckets():
+    import paper_1802_06130_amd as M
+    torch = _torch()
+    gb = gpu_bank(_bank(1, 2, 3), 3, coeff_dtype=torch.float16)
+    with pytest.raises(M.MdnError):
+        M.Plan(gb, M.F16, max_images=4)
