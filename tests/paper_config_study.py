@@ -1,0 +1,68 @@
+"""The paper's experimental configuration (Section 5) against the 4-level 7x7/7x7, 24x3x3-bucket
+configuration the rest of this repository measures: quality and throughput on one GPU.
+
+Paper configuration at noise sigma: 16x16x16 buckets, 7x7 denoise / 5x5 upscale filters (5x5 / 3x3
+below sigma 10), as many levels as bring the coarsest level's noise below 2 (oracle.paper_setup).
+Both banks are trained on the GPU from 64 seeded 256x256 pairs with the eight symmetries (Section 5),
+ridge 1e-3, float32 coefficients; PSNR over 8 held-out seeded 512x512 images. Throughput: mdn_denoise
+of one seeded 4032x3024 RGB frame, float32 storage (the path that serves banks too large for LDS),
+HIP events, median of 5. Synthetic scenes stand in for the paper's corpus and test set.
+
+Run on a GPU machine:  python tests/paper_config_study.py  (prints one JSON object)
+"""
+
+import json
+import os
+import sys
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(HERE))
+
+import oracle as O  # noqa: E402
+import synth  # noqa: E402
+
+
+def _time_denoise(M, torch, bank, frame):
+    out = torch.empty_like(frame)
+    M.denoise(frame, bank, out=out)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(5)]
+    for a, b in ev:
+        a.record()
+        M.denoise(frame, bank, out=out)
+        b.record()
+    torch.cuda.synchronize()
+    return float(np.median([a.elapsed_time(b) for a, b in ev]))
+
+
+def main():
+    import torch
+    import paper_1802_06130_amd as M
+    dev = torch.device("cuda:0")
+    frame = torch.from_numpy(synth.noisy_pair(7, 3024, 4032, 3, 25)[0]).to(dev)
+    res = {}
+    for sigma in (5.0, 25.0, 50.0):
+        pairs = [synth.noisy_pair(8200 + i, 256, 256, 3, sigma) for i in range(64)]
+        dp = [(torch.from_numpy(z).to(dev), torch.from_numpy(u).to(dev)) for z, u in pairs]
+        tests = [synth.noisy_pair(9200 + i, 512, 512, 3, sigma) for i in range(8)]
+        row = {"noisy_psnr_db": round(float(np.mean([O.psnr(z, u) for z, u in tests])), 4)}
+        L, rf, rg, (qt, qs, qc) = O.paper_setup(sigma)
+        for name, cfg in (("paper", (L, qt, qs, qc, rf, rg)), ("repo_4level_216", (3, 24, 3, 3, 3, 3))):
+            l_, qt_, qs_, qc_, rf_, rg_ = cfg
+            bank, _, fbs = M.train_multiscale(dp, l_, qt_, qs_, qc_, rf_, rg_, 1e-3, augment=True)
+            ps = [O.psnr(M.denoise(torch.from_numpy(z).to(dev), bank).cpu().numpy().astype(np.float64), u)
+                  for z, u in tests]
+            ms = _time_denoise(M, torch, bank, frame)
+            row[name] = {"levels": l_ + 1, "buckets": qt_ * qs_ * qc_, "radius_f": rf_, "radius_g": rg_,
+                         "psnr_db": round(float(np.mean(ps)), 4), "fallback_systems": [int(f) for f in fbs],
+                         "frame_ms_f32": round(ms, 3), "MP_s_f32": round(3024 * 4032 / ms * 1e-3, 1)}
+            del bank
+            torch.cuda.empty_cache()
+        res[f"sigma_{int(sigma)}"] = row
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()
