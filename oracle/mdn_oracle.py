@@ -34,7 +34,7 @@ __all__ = [
     "accumulate_level", "solve_level", "train_single", "train_multiscale",
     "CrossGramStats", "accumulate_level_cross", "solve_level_cross", "apply_level_cross",
     "psnr", "round_storage", "dihedral", "augment_pairs", "luma", "selector_image",
-    "down2_noise_gain", "pyramid_noise_gain", "paper_setup",
+    "down2_noise_gain", "pyramid_noise_gain", "paper_setup", "add_phase",
 ]
 
 # --------------------------------------------------------------------------------------
@@ -296,15 +296,30 @@ def selector_image(z_sel: np.ndarray, selector: str = "rgb") -> np.ndarray:
     return z_sel
 
 
-def select(z_sel: np.ndarray, q_theta: int, t_s, t_c, return_margin: bool = False, selector: str = "rgb"):
+def add_phase(s: np.ndarray, phases: int) -> np.ndarray:
+    """Phase-aware buckets (reading of the non-integer "i/2" of Eq. (9) for odd i): with phases = 4
+    the parity of the pixel's row and column, p = 2 (y mod 2) + (x mod 2), joins the bucket index as
+    s' = 4 s + p, so that each bucket has one upscale (and denoise) filter per phase of i relative to
+    the coarser grid. phases = 1 leaves s as it is (one phase-blind filter per bucket)."""
+    if phases == 1:
+        return s
+    if phases != 4:
+        raise ValueError(phases)
+    H, W = np.shape(s)
+    p = 2 * (np.arange(H)[:, None] % 2) + (np.arange(W)[None, :] % 2)
+    return 4 * np.asarray(s, dtype=np.int64) + p
+
+
+def select(z_sel: np.ndarray, q_theta: int, t_s, t_c, return_margin: bool = False, selector: str = "rgb",
+           phases: int = 1):
     """Filter selector s(i) from the image the structure tensor is taken on.
 
     Colour images: z_sel is RGB (the channels summed in Eq. (6)), or its luma with
-    selector="luma"; grey: one channel.
+    selector="luma"; grey: one channel. phases = 4: phase-aware buckets (add_phase).
     """
     a, b, c = structure_tensor(selector_image(z_sel, selector))
     theta, strength, coh = eigen_features(a, b, c)
-    s = quantize(theta, strength, coh, q_theta, t_s, t_c)
+    s = add_phase(quantize(theta, strength, coh, q_theta, t_s, t_c), phases)
     if return_margin:
         return s, select_margins(a, b, c, theta, strength, coh, q_theta, t_s, t_c)
     return s
@@ -333,6 +348,7 @@ class LevelBank:
     radius_f: Optional[int]
     coeffs: np.ndarray
     selector: str = "rgb"          # "rgb" (Eq. (6) over R, G, B) or "luma"
+    phases: int = 1                # 1, or 4 phase-aware buckets (add_phase); coeffs then has 4K rows
 
     @property
     def q_s(self):
@@ -344,7 +360,7 @@ class LevelBank:
 
     @property
     def K(self):
-        return self.q_theta * self.q_s * self.q_c
+        return self.q_theta * self.q_s * self.q_c * self.phases
 
     @property
     def taps_f(self):
@@ -394,7 +410,7 @@ def denoise(img: np.ndarray, bank: Bank, storage=None, return_index_maps: bool =
     img = round_storage(img, storage)
     if not multiscale:
         lb = bank.levels[0]
-        s = select(img, lb.q_theta, lb.t_s, lb.t_c, selector=lb.selector)
+        s = select(img, lb.q_theta, lb.t_s, lb.t_c, selector=lb.selector, phases=lb.phases)
         out = from_filter_space(apply_level(to_filter_space(img), s, lb))
         out = round_storage(out, storage)
         return (out, [s]) if return_index_maps else out
@@ -403,7 +419,7 @@ def denoise(img: np.ndarray, bank: Bank, storage=None, return_index_maps: bool =
     maps = [None] * L
     for lev in range(L - 1, -1, -1):
         lb = bank.levels[lev]
-        s = select(pyr[lev], lb.q_theta, lb.t_s, lb.t_c, selector=lb.selector)
+        s = select(pyr[lev], lb.q_theta, lb.t_s, lb.t_c, selector=lb.selector, phases=lb.phases)
         maps[lev] = s
         u = apply_level(to_filter_space(pyr[lev]), s, lb, u_coarse=u)
         if lev > 0:
@@ -621,7 +637,8 @@ def augment_pairs(pairs):
 
 
 def train_single(pairs, q_theta: int, q_s: int, q_c: int, radius: int, lam: float,
-                 t_s=None, t_c=None, n_min=None, augment: bool = False, selector: str = "rgb"):
+                 t_s=None, t_c=None, n_min=None, augment: bool = False, selector: str = "rgb",
+                 phases: int = 1):
     """Single-scale bank (Eq. (1), (7)-(8)) from (noisy, clean) pairs of (C, H, W) images.
 
     augment: train on the eight symmetries of every pair (Section 5).
@@ -635,21 +652,21 @@ def train_single(pairs, q_theta: int, q_s: int, q_c: int, radius: int, lam: floa
         co = np.concatenate([f[1] for f in feats])
         t_s = thresholds_from_features(st, q_s) if t_s is None else np.asarray(t_s, float)
         t_c = thresholds_from_features(co, q_c) if t_c is None else np.asarray(t_c, float)
-    K = q_theta * q_s * q_c
+    K = q_theta * q_s * q_c * phases
     C = zs[0].shape[0]
     D = (2 * radius + 1) ** 2
     stats = GramStats.zeros(K, C, D)
     for (z, u) in pairs:
-        s = select(np.asarray(z, np.float64), q_theta, t_s, t_c, selector=selector)
+        s = select(np.asarray(z, np.float64), q_theta, t_s, t_c, selector=selector, phases=phases)
         accumulate_level(stats, s, to_filter_space(z), to_filter_space(u), radius)
     coeffs, fb = solve_level(stats, lam, n_min)
-    lb = LevelBank(q_theta, np.asarray(t_s, float), np.asarray(t_c, float), radius, None, coeffs, selector)
+    lb = LevelBank(q_theta, np.asarray(t_s, float), np.asarray(t_c, float), radius, None, coeffs, selector, phases)
     return Bank([lb]), stats, fb
 
 
 def train_multiscale(pairs, n_trained_levels: int, q_theta: int, q_s: int, q_c: int,
                      radius_f: int, radius_g: int, lam: float, thresholds=None, n_min=None,
-                     storage=None, augment: bool = False, selector: str = "rgb"):
+                     storage=None, augment: bool = False, selector: str = "rgb", phases: int = 1):
     """Multiscale bank, trained from the second-coarsest level down (Section 4).
 
     Level l is fitted with u^{l+1} = the output of the already trained level l+1
@@ -659,6 +676,7 @@ def train_multiscale(pairs, n_trained_levels: int, q_theta: int, q_s: int, q_c: 
     ``augment``: train on the eight symmetries of every pair (Section 5); each
     symmetric copy is a pair of its own, with its own pyramid and cascade.
     ``selector``: structure tensor of the colour levels ("rgb") or of their luma ("luma").
+    ``phases``: 1, or 4 for phase-aware buckets (add_phase).
     """
     if augment:
         pairs = augment_pairs(pairs)
@@ -677,17 +695,17 @@ def train_multiscale(pairs, n_trained_levels: int, q_theta: int, q_s: int, q_c: 
             feats = [level_features(p[lev], selector) for p in pz]
             t_s = thresholds_from_features(np.concatenate([f[0] for f in feats]), q_s)
             t_c = thresholds_from_features(np.concatenate([f[1] for f in feats]), q_c)
-        K = q_theta * q_s * q_c
+        K = q_theta * q_s * q_c * phases
         D = (2 * radius_f + 1) ** 2 + (2 * radius_g + 1) ** 2
         stats = GramStats.zeros(K, C, D)
         smaps = []
         for i in range(len(pairs)):
-            s = select(pz[i][lev], q_theta, t_s, t_c, selector=selector)
+            s = select(pz[i][lev], q_theta, t_s, t_c, selector=selector, phases=phases)
             smaps.append(s)
             accumulate_level(stats, s, to_filter_space(pz[i][lev]), to_filter_space(pu[i][lev]),
                              radius_g, radius_f, uhat[i])
         coeffs, fb = solve_level(stats, lam, n_min)
-        lb = LevelBank(q_theta, t_s, t_c, radius_g, radius_f, coeffs, selector)
+        lb = LevelBank(q_theta, t_s, t_c, radius_g, radius_f, coeffs, selector, phases)
         levels[lev] = lb
         stats_all[lev] = stats
         fallbacks[lev] = fb

@@ -665,3 +665,76 @@ def test_paper_setup_levels_and_footprints(sigma, want):
     L, rf, rg, q = O.paper_setup(sigma)
     assert (L, rf, rg) == want and q == (16, 16, 16)
     assert sigma * O.pyramid_noise_gain(L) < 2.0 <= sigma * O.pyramid_noise_gain(L - 1)
+
+
+# ----------------------------------------------------------------------------- phase-aware buckets (Eq. (9), "i/2")
+
+def test_phase_index_layout():
+    s = np.arange(12).reshape(3, 4)
+    sp = O.add_phase(s, 4)
+    assert sp[0, 0] == 0 and sp[0, 1] == 4 * 1 + 1 and sp[1, 0] == 4 * 4 + 2 and sp[1, 1] == 4 * 5 + 3
+    assert np.array_equal(sp // 4, s) and np.array_equal(O.add_phase(s, 1), s)
+
+
+def test_phase_copies_of_a_blind_bank_change_nothing():
+    """Four identical phase rows per bucket give exactly the phase-blind cascade."""
+    pairs = [synth.noisy_pair(70 + i, 48, 48, 3, 25) for i in range(2)]
+    pairs = [(z.astype(np.float64), u.astype(np.float64)) for z, u in pairs]
+    bank, _, _ = O.train_multiscale(pairs, 2, 8, 2, 2, 2, 2, 1e-3)
+    rep = O.Bank([O.LevelBank(lb.q_theta, lb.t_s, lb.t_c, lb.radius_g, lb.radius_f,
+                              np.repeat(lb.coeffs, 4, axis=0), phases=4) for lb in bank.levels])
+    z, _ = synth.noisy_pair(77, 50, 62, 3, 25)
+    assert np.array_equal(O.denoise(z, rep), O.denoise(z, bank))
+
+
+def test_phase_aware_upscale_reproduces_a_ramp():
+    """Each fine pixel i sits at (i - 1/2)/2 on the coarse grid (down2 is centred at 2m + 1/2):
+    m - 1/4 for even i and m + 1/4 for odd i. Bilinear upscale filters per phase, 3/4 of the
+    nearest coarse sample and 1/4 of the next one on the pixel's side, therefore reproduce a
+    linear ramp exactly; one phase-blind filter cannot serve both parities."""
+    H, W = 24, 28
+    yy, xx = np.mgrid[0:H, 0:W].astype(float)
+    a, bx, by = 0.3, 0.011, -0.007
+    fine = a + bx * xx + by * yy
+    cy, cx = np.mgrid[0:H // 2, 0:W // 2].astype(float)
+    coarse = (a + bx * (2 * cx + 0.5) + by * (2 * cy + 0.5))[None]
+    r = 1
+    taps = O.tap_offsets(r)
+    K, q_theta = 2, 2                       # one orientation bin pair, one strength and coherence bin
+    coeffs = np.zeros((4 * K, 1, len(taps) + len(taps)))
+    for p in range(4):
+        wy = {-1: 0.25, 0: 0.75, 1: 0.0} if p // 2 == 0 else {-1: 0.0, 0: 0.75, 1: 0.25}
+        wx = {-1: 0.25, 0: 0.75, 1: 0.0} if p % 2 == 0 else {-1: 0.0, 0: 0.75, 1: 0.25}
+        for t, (dy, dx) in enumerate(taps):
+            coeffs[[4 * k + p for k in range(K)], 0, t] = wy[dy] * wx[dx]
+    lb = O.LevelBank(q_theta, np.array([]), np.array([]), r, r, coeffs, phases=4)
+    s = O.add_phase(np.zeros((H, W), np.int64), 4)
+    out = O.apply_level(fine[None] * 0, s, lb, u_coarse=coarse)
+    core = (slice(2, H - 2), slice(2, W - 2))
+    assert np.max(np.abs(out[0][core] - fine[core])) < 1e-14
+    blind = O.LevelBank(q_theta, np.array([]), np.array([]), r, r, coeffs[0::4], phases=1)
+    out_b = O.apply_level(fine[None] * 0, np.zeros((H, W), np.int64), blind, u_coarse=coarse)
+    assert np.max(np.abs(out_b[0][core] - fine[core])) > 1e-3
+
+
+def test_planted_phase_aware_recovery():
+    """Noise-free targets made by phase-dependent planted filters are recovered exactly with
+    phases = 4 (lambda = 0) and not by the phase-blind fit."""
+    rng = np.random.default_rng(42)
+    q_theta, r = 2, 1
+    K = q_theta * 2 * 2 * 4
+    planted = rng.normal(0, 0.3, (K, 1, 9))
+    zs = [rng.uniform(0, 1, (1, 40, 40)) for _ in range(4)]
+    t_s, t_c = [1e9], [1e9]                 # every pixel in strength and coherence bin 0
+    pairs = []
+    for z in zs:
+        s = O.select(z, q_theta, t_s, t_c, phases=4)
+        lb = O.LevelBank(q_theta, np.array(t_s), np.array(t_c), r, None, planted, phases=4)
+        pairs.append((z, O.apply_level(z, s, lb)))
+    bank, _, fb = O.train_single(pairs, q_theta, 2, 2, r, 0.0, t_s=t_s, t_c=t_c, n_min=9, phases=4)
+    idx = [4 * b + p for b in (0, 4) for p in range(4)]      # buckets (q_theta bin 0 or 1, 0, 0) x phases
+    assert not fb[idx].any()
+    assert np.max(np.abs(bank.levels[0].coeffs[idx] - planted[idx])) < 1e-10
+    blind, _, _ = O.train_single(pairs, q_theta, 2, 2, r, 0.0, t_s=t_s, t_c=t_c, n_min=9)
+    for b in (0, 4):
+        assert np.max(np.abs(blind.levels[0].coeffs[b] - planted[4 * b])) > 1e-3
