@@ -78,7 +78,11 @@ typedef struct {
  * colour level instead (float64; the luma-only analysis Section 3 compares against, Fig. 2).
  * coeffs[k][c] holds taps_f = (2*radius_f+1)^2 upscale taps applied to the coarser output at
  * floor(i/2) + j, then taps_g = (2*radius_g+1)^2 taps applied to this level's input at i + j,
- * both row-major over (dy, dx). */
+ * both row-major over (dy, dx).
+ * phases = 4 makes the buckets phase-aware (a reading of the non-integer i/2 of Eq. (9) for odd
+ * i): the parity of the pixel on the coarser grid, p = 2 (y mod 2) + (x mod 2), joins the index as
+ * s' = 4 s + p, so that every bucket has one filter pair per phase; all sizes and maps then count
+ * 4K buckets. */
 typedef struct {
     int32_t q_theta;      /* 2..64, even */
     int32_t q_s;          /* 1..16 */
@@ -88,6 +92,8 @@ typedef struct {
     int32_t channels;     /* 1 or 3, must match the images */
     int32_t coeff_dtype;  /* mdn_dtype of coeffs */
     int32_t selector;     /* mdn_selector: MDN_SELECT_RGB (0) or MDN_SELECT_LUMA (1) */
+    int32_t phases;       /* 1, or 4: phase-aware buckets (see above); coeffs then has 4K rows */
+    int32_t reserved;     /* must be 0 */
     const double* t_s;    /* HOST, q_s-1 ascending strength thresholds */
     const double* t_c;    /* HOST, q_c-1 ascending coherence thresholds */
     const void*   coeffs; /* DEVICE, [K][channels][taps_f + taps_g] */

@@ -40,7 +40,8 @@ class MdnImage(ct.Structure):
 class MdnLevel(ct.Structure):
     _fields_ = [("q_theta", ct.c_int32), ("q_s", ct.c_int32), ("q_c", ct.c_int32),
                 ("radius_f", ct.c_int32), ("radius_g", ct.c_int32), ("channels", ct.c_int32),
-                ("coeff_dtype", ct.c_int32), ("selector", ct.c_int32),
+                ("coeff_dtype", ct.c_int32), ("selector", ct.c_int32), ("phases", ct.c_int32),
+                ("reserved", ct.c_int32),
                 ("t_s", ct.POINTER(ct.c_double)), ("t_c", ct.POINTER(ct.c_double)),
                 ("coeffs", ct.c_void_p)]
 
@@ -126,9 +127,10 @@ class Level:
     """One trained level: thresholds on the host, coefficients on the device."""
 
     def __init__(self, q_theta: int, t_s: Sequence[float], t_c: Sequence[float], radius_g: int,
-                 radius_f: Optional[int], coeffs, channels: int, selector: int = 0):
+                 radius_f: Optional[int], coeffs, channels: int, selector: int = 0, phases: int = 1):
         self.q_theta = int(q_theta)
         self.selector = int(selector)          # SELECT_RGB or SELECT_LUMA
+        self.phases = int(phases)              # 1, or 4 phase-aware buckets
         self.t_s = np.ascontiguousarray(np.asarray(t_s, dtype=np.float64))
         self.t_c = np.ascontiguousarray(np.asarray(t_c, dtype=np.float64))
         self.radius_g = int(radius_g)
@@ -140,11 +142,11 @@ class Level:
 
     @property
     def K(self):
-        return self.q_theta * (len(self.t_s) + 1) * (len(self.t_c) + 1)
+        return self.q_theta * (len(self.t_s) + 1) * (len(self.t_c) + 1) * self.phases
 
     def desc(self) -> MdnLevel:
         return MdnLevel(self.q_theta, len(self.t_s) + 1, len(self.t_c) + 1, self.radius_f, self.radius_g,
-                        self.channels, _dtype_code(self.coeffs), self.selector,
+                        self.channels, _dtype_code(self.coeffs), self.selector, self.phases, 0,
                         ct.cast(self._ts_arr, ct.POINTER(ct.c_double)),
                         ct.cast(self._tc_arr, ct.POINTER(ct.c_double)),
                         ct.c_void_p(self.coeffs.data_ptr()))
@@ -406,7 +408,7 @@ def level_thresholds(zs, q_s: int, q_c: int, selector: int = 0):
 
 def train_single(pairs, q_theta: int, q_s: int, q_c: int, radius: int, lam: float, thresholds=None,
                  precision: int = GRAM_F32, coeff_dtype=None, min_count=None, augment: bool = False,
-                 selector: int = 0):
+                 selector: int = 0, phases: int = 1):
     """Single-scale bank (Eq. (1), (7)-(8)) from (noisy, clean) (C, H, W) device tensors;
     augment: train on the eight symmetries of every pair (Section 5); selector: SELECT_RGB or
     SELECT_LUMA."""
@@ -418,24 +420,25 @@ def train_single(pairs, q_theta: int, q_s: int, q_c: int, radius: int, lam: floa
         t_s, t_c = level_thresholds([z for z, _ in pairs], q_s, q_c, selector)
     else:
         t_s, t_c = thresholds
-    K = q_theta * (len(t_s) + 1) * (len(t_c) + 1)
+    K = q_theta * (len(t_s) + 1) * (len(t_c) + 1) * phases
     dummy = torch.zeros((K, C, (2 * radius + 1) ** 2), dtype=torch.float32, device=pairs[0][0].device)
-    sel = Level(q_theta, t_s, t_c, radius, None, dummy, C, selector)
+    sel = Level(q_theta, t_s, t_c, radius, None, dummy, C, selector, phases)
     g = Gram(K, C, radius, None, device=pairs[0][0].device)
     ws = None
     for z, u in pairs:
         ws = train_accumulate(g, z, u, sel, precision=precision, ws=ws)
     co, nfb = train_solve(g, lam, min_count, coeff_dtype)
-    return Bank([Level(q_theta, t_s, t_c, radius, None, co, C, selector)]), g, nfb
+    return Bank([Level(q_theta, t_s, t_c, radius, None, co, C, selector, phases)]), g, nfb
 
 
 def train_multiscale(pairs, n_trained_levels: int, q_theta: int, q_s: int, q_c: int, radius_f: int,
                      radius_g: int, lam: float, thresholds=None, precision: int = GRAM_F32, coeff_dtype=None,
-                     min_count=None, storage=None, augment: bool = False, selector: int = 0):
+                     min_count=None, storage=None, augment: bool = False, selector: int = 0, phases: int = 1):
     """Multiscale bank trained from the second-coarsest level down (Section 4); pairs are
     (noisy, clean) (C, H, W) device tensors. Returns (Bank, grams, fallback counts).
     augment: train on the eight symmetries of every pair (Section 5), each its own pair;
-    selector: SELECT_RGB (colour structure tensor) or SELECT_LUMA."""
+    selector: SELECT_RGB (colour structure tensor) or SELECT_LUMA; phases: 1 or 4 (phase-aware
+    buckets)."""
     torch = _torch()
     if augment:
         pairs = augment_pairs(pairs)
@@ -455,15 +458,15 @@ def train_multiscale(pairs, n_trained_levels: int, q_theta: int, q_s: int, q_c: 
             t_s, t_c = thresholds[lev]
         else:
             t_s, t_c = level_thresholds([p[lev] for p in pz], q_s, q_c, selector)
-        K = q_theta * (len(t_s) + 1) * (len(t_c) + 1)
+        K = q_theta * (len(t_s) + 1) * (len(t_c) + 1) * phases
         sel = Level(q_theta, t_s, t_c, radius_g, radius_f, torch.zeros((K, C, D), dtype=torch.float32, device=dev), C,
-                    selector)
+                    selector, phases)
         g = Gram(K, C, radius_g, radius_f, device=dev)
         for i in range(len(pairs)):
             ws = train_accumulate(g, pz[i][lev], pu[i][lev], sel, u_coarse=uhat[i], precision=precision,
                                   coarse_color=coarse_color, ws=ws)
         co, nfb = train_solve(g, lam, min_count, coeff_dtype)
-        lvl = Level(q_theta, t_s, t_c, radius_g, radius_f, co, C, selector)
+        lvl = Level(q_theta, t_s, t_c, radius_g, radius_f, co, C, selector, phases)
         levels[lev], grams[lev], fbs[lev] = lvl, g, nfb
         uhat = [apply_level(pz[i][lev], lvl, u_coarse=uhat[i], coarse_color=coarse_color,
                             out_dtype=pz[i][lev].dtype) for i in range(len(pairs))]

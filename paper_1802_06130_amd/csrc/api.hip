@@ -69,7 +69,9 @@ mdn_status check_level(const mdn_level* lv, int channels) {
         return fail(MDN_EINVAL, "level: q_theta must be even in [2, %d]", kMaxTheta);
     if (lv->q_s < 1 || lv->q_s > kMaxThr || lv->q_c < 1 || lv->q_c > kMaxThr)
         return fail(MDN_EINVAL, "level: q_s and q_c must be in [1, %d]", kMaxThr);
-    const int K = lv->q_theta * lv->q_s * lv->q_c;
+    if (lv->phases != 1 && lv->phases != 4) return fail(MDN_EINVAL, "level: phases must be 1 or 4");
+    if (lv->reserved != 0) return fail(MDN_EINVAL, "level: reserved field must be 0");
+    const int K = level_buckets(*lv);
     if (K > 65536) return fail(MDN_ENOTSUP, "level: K = %d > 65536 buckets is not supported (uint16 selector)", K);
     if (lv->channels != channels) return fail(MDN_EINVAL, "level: channels %d != image channels %d", lv->channels, channels);
     if (lv->coeff_dtype != MDN_F32 && lv->coeff_dtype != MDN_F16) return fail(MDN_EINVAL, "level: unknown coeff dtype");
@@ -350,7 +352,7 @@ mdn_status mdn_train_accumulate(const mdn_gram* g, const mdn_image* z, const mdn
         return fail(MDN_EINVAL, "target must match z (RGB or grey)");
     if (z->channels != g->channels) return fail(MDN_EINVAL, "gram channels differ from the image's");
     if ((st = check_level(sel, z->channels))) return st;
-    if (sel->q_theta * sel->q_s * sel->q_c != g->K) return fail(MDN_EINVAL, "selector K differs from gram K");
+    if (level_buckets(*sel) != g->K) return fail(MDN_EINVAL, "selector K differs from gram K");
     if (precision != MDN_GRAM_F32 && precision != MDN_GRAM_BF16X3) return fail(MDN_EINVAL, "unknown precision");
     if (g->radius_f >= 1) {
         if ((st = check_image(u_coarse, "u_coarse"))) return st;

@@ -253,7 +253,7 @@ mdn_status build_batch(const mdn_level* lv, const SelWalkArgs* selc, int L, int 
         bl->walk[l].n_strips = begin;
         bl->walk[l].coeffs = lv[l].coeffs;
         bl->walk[l].coeff_dtype = lv[l].coeff_dtype;
-        bl->walk[l].K = lv[l].q_theta * lv[l].q_s * lv[l].q_c;
+        bl->walk[l].K = level_buckets(lv[l]);
         th += al256(sizeof(WalkImage) * n);
         td += al256(sizeof(WalkImage) * n);
     }

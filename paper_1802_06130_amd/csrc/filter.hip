@@ -223,6 +223,7 @@ __global__ __launch_bounds__(256) void k_select_apply(FilterArgs a) {
                 sv[k] = 0;
             } else {
                 sv[k] = bucket_of(sa / 25.0, sb / 25.0, sc / 25.0, a.sel);
+                if (a.sel.phases == 4) sv[k] = 4 * sv[k] + (((y0 + py) & 1) << 1) + ((x0 + tx) & 1);
             }
         }
     } else {
@@ -375,6 +376,7 @@ void fill_select_arg(const mdn_level& lvl, SelectArg& sa) {
     sa.q_s = lvl.q_s;
     sa.q_c = lvl.q_c;
     sa.luma = lvl.selector == MDN_SELECT_LUMA && lvl.channels == 3;
+    sa.phases = lvl.phases;
     for (int j = 0; j < lvl.q_s - 1; ++j) sa.t_s[j] = lvl.t_s[j];
     for (int j = 0; j < lvl.q_c - 1; ++j) sa.t_c[j] = lvl.t_c[j];
     orientation_boundaries(lvl.q_theta, sa.bcos, sa.bsin);
@@ -433,7 +435,7 @@ mdn_status launch_select_apply(const mdn_image& z, const mdn_image* uc, const vo
         fa.out_rgb = out->color == MDN_RGB;
     }
     fa.coeffs = lvl.coeffs;
-    fa.K = lvl.q_theta * lvl.q_s * lvl.q_c;
+    fa.K = level_buckets(lvl);
     fill_select_arg(lvl, fa.sel);
     const bool apply = out != nullptr;
     const int C = z.channels;

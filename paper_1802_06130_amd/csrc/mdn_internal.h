@@ -78,6 +78,7 @@ __device__ __forceinline__ double luma_d(double r, double g, double b) {
 struct SelectArg {
     int32_t q_theta, q_s, q_c;
     int32_t luma;               // colour input: structure tensor of the luma only
+    int32_t phases, pad;        // 4: bucket s' = 4 s + 2 (y mod 2) + (x mod 2)
     double t_s[kMaxThr];
     double t_c[kMaxThr];
     // Unit vectors at the orientation-bin boundaries of the doubled angle, k = 1 .. q_theta/2 - 1,
@@ -101,7 +102,8 @@ inline mdn_status launch_down2(const mdn_image& in, const mdn_image& out, hipStr
     return launch_down2_walk(in, out, st);
 }
 // Selector maps hold uint8 when K <= 256 and uint16 otherwise (s_pitch in elements).
-inline bool wide_selector(const mdn_level& lvl) { return lvl.q_theta * lvl.q_s * lvl.q_c > 256; }
+inline int level_buckets(const mdn_level& lvl) { return lvl.q_theta * lvl.q_s * lvl.q_c * lvl.phases; }
+inline bool wide_selector(const mdn_level& lvl) { return level_buckets(lvl) > 256; }
 mdn_status launch_select_apply(const mdn_image& z, const mdn_image* uc, const void* s_in,
                                int64_t s_pitch, void* s_out, const mdn_level& lvl,
                                const mdn_image* out, hipStream_t st);

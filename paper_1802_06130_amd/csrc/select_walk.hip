@@ -266,7 +266,8 @@ __global__ __launch_bounds__(64 * kWaves, MDN_SEL_WAVES_PER_SIMD) void k_select_
                 const double sa = (((hr[0].A + hr[1].A) + hr[2].A) + hr[3].A) + hr[4].A;
                 const double sb = (((hr[0].B + hr[1].B) + hr[2].B) + hr[3].B) + hr[4].B;
                 const double sc = (((hr[0].C + hr[1].C) + hr[2].C) + hr[3].C) + hr[4].C;
-                const int s = bucket<QS, QC, MQ, NSTEP>(sa, sb, sc, a, bt);
+                int s = bucket<QS, QC, MQ, NSTEP>(sa, sb, sc, a, bt);
+                if (a.phases == 4) s = 4 * s + ((y & 1) << 1) + (x & 1);
                 if (out_lane && y < ye) *((MDN_GLOBAL TS*)im.s + (uint32_t)y * (uint32_t)im.s_pitch + (uint32_t)x) = (TS)s;
             }, std::make_integer_sequence<int, 10>{});
         }
@@ -289,6 +290,7 @@ void fill_sel_consts(const mdn_level& lvl, SelWalkArgs& a) {
     a.q_c = lvl.q_c;
     a.half = lvl.q_theta / 2;
     a.luma = lvl.selector == MDN_SELECT_LUMA && lvl.channels == 3;
+    a.phases = lvl.phases;
     for (int j = 0; j < lvl.q_s - 1; ++j) {
         const double t = lvl.t_s[j] > 0.0 ? lvl.t_s[j] : 0.0;
         a.s_lim[j] = 100.0 * t * t;
@@ -311,8 +313,8 @@ mdn_status launch_select_args(const SelWalkArgs& a, int channels, int z_dtype, h
     const int blocks = (a.n_strips + kWaves - 1) / kWaves;
     const int grid = blocks < 8 * ncu ? blocks : 8 * ncu;
     // 3 x 3 strength/coherence bins with 24 or 16 orientation bins get fixed-count instances
-    const int spec = (a.q_s == 3 && a.q_c == 3) ? (a.q_theta == 24 ? 1 : a.q_theta == 16 ? 2 : 0) : 0;
-    const bool wide = a.q_theta * a.q_s * a.q_c > 256;      // uint16 selector map
+    const bool wide = a.q_theta * a.q_s * a.q_c * a.phases > 256;      // uint16 selector map
+    const int spec = (!wide && a.q_s == 3 && a.q_c == 3) ? (a.q_theta == 24 ? 1 : a.q_theta == 16 ? 2 : 0) : 0;
 #define MDN_SEL_LAUNCH(TZ_, C_, L_)                                                                 \
     do {                                                                                               \
         if (spec == 1) k_select_walk<TZ_, uint8_t, C_, L_, 3, 3, 5, 0><<<grid, 64 * kWaves, 0, st>>>(a);         \

@@ -330,7 +330,7 @@ public:
                 a.n_strips = L.strips;
                 a.coeffs = lv.coeffs;
                 a.coeff_dtype = lv.coeff_dtype;
-                a.K = lv.q_theta * lv.q_s * lv.q_c;
+                a.K = level_buckets(lv);
                 st = launch_walk_args(a, L.k.zd, storage_, L.k.od, comp_);
             }
             if (st)

@@ -295,7 +295,7 @@ __global__ __launch_bounds__(64 * MDN_WALK_WAVES) void k_walk(WalkArgs a) {
 }  // namespace
 
 bool walk_supported(const mdn_level& lvl, int channels) {
-    return channels == 3 && lvl.radius_f == 3 && lvl.radius_g == 3 && lvl.q_theta * lvl.q_s * lvl.q_c <= kMaxK;
+    return channels == 3 && lvl.radius_f == 3 && lvl.radius_g == 3 && lvl.phases == 1 && level_buckets(lvl) <= kMaxK;
 }
 
 size_t walk_lds_bytes(int K) { return (size_t)K * bank_stride(K); }
@@ -398,7 +398,7 @@ mdn_status launch_walk(const mdn_image& z, const mdn_image& uc, const mdn_level&
     a.n_strips = a.single.nsx * ((z.height + a.single.rows - 1) / a.single.rows);
     a.coeffs = lvl.coeffs;
     a.coeff_dtype = lvl.coeff_dtype;
-    a.K = lvl.q_theta * lvl.q_s * lvl.q_c;
+    a.K = level_buckets(lvl);
     return launch_walk_args(a, z.dtype, uc.dtype, out.dtype, st);
 }
 

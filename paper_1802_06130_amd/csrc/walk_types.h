@@ -52,6 +52,7 @@ struct SelWalkArgs {
     int32_t n_imgs, n_strips;
     int32_t q_theta, q_s, q_c, half;
     int32_t luma;               // RGB input: structure tensor of its float64 luma only
+    int32_t phases;             // 4: bucket s' = 4 s + 2 (y mod 2) + (x mod 2)
     double s_lim[kMaxThr];      // 100 t^2: box sums of squared differences are 100 x the box mean
     double c_k2[kMaxThr];       // (2t/(1+t^2))^2, or -1 when t <= 0 (always reached)
     double bcos[kMaxTheta / 2], bsin[kMaxTheta / 2];

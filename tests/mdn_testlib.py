@@ -45,7 +45,7 @@ def gpu_level(lb: O.LevelBank, channels: int, coeff_dtype=None, device="cuda"):
     dt = coeff_dtype or torch.float32
     co = torch.tensor(np.ascontiguousarray(lb.coeffs), dtype=torch.float64).to(dt).to(device)
     sel = M.SELECT_LUMA if lb.selector == "luma" else M.SELECT_RGB
-    return M.Level(lb.q_theta, lb.t_s, lb.t_c, lb.radius_g, lb.radius_f, co, channels, sel)
+    return M.Level(lb.q_theta, lb.t_s, lb.t_c, lb.radius_g, lb.radius_f, co, channels, sel, lb.phases)
 
 
 def gpu_bank(bank: O.Bank, channels: int, coeff_dtype=None, device="cuda"):
@@ -59,7 +59,7 @@ def index_parity(s_gpu: np.ndarray, z_level: np.ndarray, lb: O.LevelBank):
     Returns (mismatch mask, number of mismatches, number of near-boundary pixels).
     """
     s_ref, margin = O.select(np.asarray(z_level, np.float64), lb.q_theta, lb.t_s, lb.t_c, return_margin=True,
-                             selector=lb.selector)
+                             selector=lb.selector, phases=lb.phases)
     mism = s_gpu.astype(np.int64) != s_ref
     near = margin < NEAR
     bad = mism & ~near

@@ -50,7 +50,7 @@ def _img(data=None, w=8, h=8, c=3, dtype=M.F32, color=M.RGB, reserved=0):
 def _level(**kw):
     ts = (ct.c_double * 2)(0.1, 0.2)
     tc = (ct.c_double * 2)(0.3, 0.6)
-    d = dict(q_theta=24, q_s=3, q_c=3, radius_f=3, radius_g=3, channels=3, coeff_dtype=M.F32, selector=0,
+    d = dict(q_theta=24, q_s=3, q_c=3, radius_f=3, radius_g=3, channels=3, coeff_dtype=M.F32, selector=0, phases=1,
              t_s=ct.cast(ts, ct.POINTER(ct.c_double)), t_c=ct.cast(tc, ct.POINTER(ct.c_double)), coeffs=0x1000)
     d.update(kw)
     lv = B.MdnLevel(**d)
@@ -70,6 +70,7 @@ def _level(**kw):
     (_img(data=0x1000), _level(channels=1), "channels"),
     (_img(data=0x1000), _level(coeffs=None), "coeffs"),
     (_img(data=0x1000), _level(selector=2), "selector"),
+    (_img(data=0x1000), _level(phases=2), "phases"),
     (B.MdnImage(0x1000, 8, 8, 3, M.F32, M.RGB, 0, 8, 1 << 28), _level(), "2 GiB"),
 ])
 def test_select_rejects_bad_arguments(img, lvl, msg):
