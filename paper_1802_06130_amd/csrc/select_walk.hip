@@ -6,9 +6,9 @@
 // dx = z(r, x+1) - z(r, x-1) (neighbouring columns from DPP wave shifts) and dy = z(r+1, x) -
 // z(r-1, x), accumulates A = sum_c dx^2, B = sum_c dx dy, C = sum_c dy^2 (four times the products
 // of the central-difference gradients: the factor is exact), replaces positions outside the image
-// by the value at the clamped position (readlane), and sums 5 neighbouring lanes (DPP on the two
-// halves of each double). A 5-row ring then gives the 5 x 5 box sums of row y, 100 times the box
-// mean (a, b, c). The bucket needs no square root or division:
+// by the value at the clamped position (readlane), and sums 5 neighbouring lanes (their values
+// exchanged through a per-wave LDS row). A 5-row ring then gives the 5 x 5 box sums of row y, 100
+// times the box mean (a, b, c). The bucket needs no square root or division:
 //   strength:  sqrt(lambda1) >= t  <=>  lambda1 >= t^2  <=>  mu >= 2 t^2 - tr      (mu^2 = (a-c)^2 + 4b^2)
 //   coherence: (sqrt(l1)-sqrt(l2))/(sqrt(l1)+sqrt(l2)) >= t  <=>  mu >= (2t / (1 + t^2)) tr   (tr > 0)
 //   orientation: the doubled-angle vector of the minor eigenvector, (c - a, -2b), against the bin
@@ -32,6 +32,7 @@ constexpr int kLanesOut = kSelLanesOut;
 #define MDN_SEL_WAVES_PER_SIMD 4
 #endif
 constexpr int kWaves = 4;
+constexpr int kHboxW = 68;          // 64 lanes + 2 pads each side
 
 __device__ __forceinline__ uint32_t shl1(uint32_t v) { return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x130, 0xF, 0xF, true); }
 __device__ __forceinline__ uint32_t shr1(uint32_t v) { return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x138, 0xF, 0xF, true); }
@@ -44,6 +45,13 @@ __device__ __forceinline__ double shl1d(double v) {
 __device__ __forceinline__ double shr1d(double v) {
     const uint64_t u = (uint64_t)__double_as_longlong(v);
     return __longlong_as_double((long long)(((uint64_t)shr1((uint32_t)(u >> 32)) << 32) | shr1((uint32_t)u)));
+}
+// Orders this wave's LDS accesses across lanes: memory operations are not moved across it (the
+// LDS itself serves one wave's requests in order).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 __device__ __forceinline__ float shl1x(float v) { return shl1f(v); }
 __device__ __forceinline__ float shr1x(float v) { return shr1f(v); }
@@ -147,11 +155,16 @@ __global__ __launch_bounds__(64 * kWaves, MDN_SEL_WAVES_PER_SIMD) void k_select_
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     __shared__ BoundaryTable bt;
+    // per wave: one row of A, B and C products with two zero pads on each side, for the 5-wide
+    // horizontal box sums (lanes exchange through LDS: no barrier is needed within a wave)
+    __shared__ double hbox[kWaves][3][kHboxW];
     for (int j = threadIdx.x; j < kMaxTheta / 2; j += 64 * kWaves) {
         bt.cs[j] = a.bcos[j];
         bt.sn[j] = a.bsin[j];
     }
+    for (int j = threadIdx.x; j < kWaves * 3 * kHboxW; j += 64 * kWaves) (&hbox[0][0][0])[j] = 0.0;
     __syncthreads();
+    double* hb = &hbox[wave][0][0];
     for (int strip = blockIdx.x * kWaves + wave; strip < a.n_strips; strip += gridDim.x * kWaves) {
         SelImage im;
         if (a.imgs == nullptr) {
@@ -214,9 +227,18 @@ __global__ __launch_bounds__(64 * kWaves, MDN_SEL_WAVES_PER_SIMD) void k_select_
                     p.C = C1;
                 }
             }
-            const double A1 = shl1d(p.A), A2 = shl1d(A1), Am1 = shr1d(p.A), Am2 = shr1d(Am1);
-            const double B1 = shl1d(p.B), B2 = shl1d(B1), Bm1 = shr1d(p.B), Bm2 = shr1d(Bm1);
-            const double C1 = shl1d(p.C), C2 = shl1d(C1), Cm1 = shr1d(p.C), Cm2 = shr1d(Cm1);
+            // the compiler must neither move this row's writes above the previous row's reads nor
+            // the reads above the writes: other lanes' addresses alias them
+            wave_sync();
+            hb[lane + 2] = p.A;
+            hb[kHboxW + lane + 2] = p.B;
+            hb[2 * kHboxW + lane + 2] = p.C;
+            wave_sync();
+            const double Am2 = hb[lane], Am1 = hb[lane + 1], A1 = hb[lane + 3], A2 = hb[lane + 4];
+            const double Bm2 = hb[kHboxW + lane], Bm1 = hb[kHboxW + lane + 1], B1 = hb[kHboxW + lane + 3],
+                         B2 = hb[kHboxW + lane + 4];
+            const double Cm2 = hb[2 * kHboxW + lane], Cm1 = hb[2 * kHboxW + lane + 1], C1 = hb[2 * kHboxW + lane + 3],
+                         C2 = hb[2 * kHboxW + lane + 4];
             return P3{((Am2 + Am1) + p.A) + (A1 + A2), ((Bm2 + Bm1) + p.B) + (B1 + B2), ((Cm2 + Cm1) + p.C) + (C1 + C2)};
         };
         auto hrow_at = [&](int r) {      // row cl(r), loading its three input rows
