@@ -386,7 +386,7 @@ def main():
         pmc_probe()
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU; this build has no multi-GPU path (images are independent "
+        print("bench.py measures one GPU; the library has no multi-GPU path (images are independent "
               "and would be routed to GPUs one by one).", file=sys.stderr)
         sys.exit(2)
 

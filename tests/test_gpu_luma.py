@@ -1,4 +1,4 @@
-"""Luma-only filter selection (the survey's selector ablation; Section 3 and Fig. 2 compare the
+"""Luma-only filter selection (an ablation of the selector: Section 3 and Fig. 2 compare the
 colour structure tensor of Eq. (6) with the luma-only analysis of earlier methods) on the GPU,
 through the C ABI, against the oracle.
 

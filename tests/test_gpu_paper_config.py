@@ -1,4 +1,4 @@
-"""The paper's experimental configuration (Section 5; the survey's NEXT-1) on the GPU, through the
+"""The paper's experimental configuration (Section 5) on the GPU, through the
 C ABI, against the oracle: 16 x 16 x 16 = 4096 buckets (uint16 selector maps), 7x7 denoise and 5x5
 upscale filters, pyramid depth from the noise level.
 

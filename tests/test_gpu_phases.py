@@ -1,4 +1,4 @@
-"""Phase-aware buckets (the survey's NEXT-2; the other reading of the non-integer i/2 of Eq. (9)):
+"""Phase-aware buckets (the other reading of the non-integer i/2 of Eq. (9)):
 the parity of the pixel on the coarser grid joins the bucket index, s' = 4 s + 2 (y mod 2) + (x mod 2),
 on the GPU through the C ABI, against the oracle.
 
