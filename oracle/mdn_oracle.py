@@ -33,7 +33,7 @@ __all__ = [
     "thresholds_from_features", "level_features", "GramStats", "patch_matrix",
     "accumulate_level", "solve_level", "train_single", "train_multiscale",
     "CrossGramStats", "accumulate_level_cross", "solve_level_cross", "apply_level_cross",
-    "psnr", "round_storage", "dihedral", "augment_pairs", "luma", "selector_image",
+    "psnr", "round_storage", "dihedral", "augment_pairs", "luma", "selector_image", "upsample2",
     "down2_noise_gain", "pyramid_noise_gain", "paper_setup", "add_phase",
 ]
 
@@ -280,15 +280,47 @@ def luma(rgb: np.ndarray) -> np.ndarray:
     return (KR * rgb[0] + KG * rgb[1] + KB * rgb[2])[None]
 
 
-def selector_image(z_sel: np.ndarray, selector: str = "rgb") -> np.ndarray:
+def _up2_axis(x: np.ndarray, axis: int, n: int) -> np.ndarray:
+    """Linear interpolation by two along one axis, onto n fine samples: coarse sample m sits at
+    fine coordinate 2m + 1/2, so fine 2m lies a quarter step left of it (3/4 of m, 1/4 of m-1) and
+    fine 2m+1 a quarter step right (3/4 of m, 1/4 of m+1); indices clamped at the edges."""
+    x = np.moveaxis(np.asarray(x, dtype=np.float64), axis, 0)
+    nc = x.shape[0]
+    i = np.arange(n)
+    m = i // 2
+    other = np.clip(np.where(i % 2 == 0, m - 1, m + 1), 0, nc - 1)
+    out = 0.75 * x[m] + 0.25 * x[other]
+    return np.moveaxis(out, 0, axis)
+
+
+def upsample2(x: np.ndarray, H: int, W: int) -> np.ndarray:
+    """Factor-two upsampling of a (C, ceil(H/2), ceil(W/2)) level onto the (C, H, W) grid of the
+    next finer level, on the pyramid's alignment (a coarse sample is centred between fine pixels
+    2m and 2m+1): separable linear interpolation, rows then columns (_up2_axis)."""
+    x = np.asarray(x, dtype=np.float64)
+    if x.shape[1] != (H + 1) // 2 or x.shape[2] != (W + 1) // 2:
+        raise ValueError("coarse level must be ceil(H/2) x ceil(W/2)")
+    return _up2_axis(_up2_axis(x, 1, H), 2, W)
+
+
+def selector_image(z_sel: np.ndarray, selector: str = "rgb", u_coarse: Optional[np.ndarray] = None) -> np.ndarray:
     """The image whose structure tensor selects the filters.
 
     "rgb": the colour image itself, the channels summed in Eq. (6) (the paper's choice).
     "luma": its luma channel alone, the structure tensor of the earlier methods that Section 3
     compares against (Fig. 2: luma alone can miss structure that is visible in colour).
     Grey images are their own luma.
+    "coarse": not the noisy level but the coarser level's denoised output u^{l+1} (in the filter
+    colour space, as the cascade of Section 4 holds it), upsampled onto this level's grid
+    (upsample2) and taken back to RGB; z_sel then only fixes the size. The alternative to
+    selecting on the noisy z^l that Eq. (9) leaves open: the coarser output has less noise but
+    half the resolution.
     """
     z_sel = np.asarray(z_sel, dtype=np.float64)
+    if selector == "coarse":
+        if u_coarse is None:
+            raise ValueError("the coarse selector needs the coarser output")
+        return from_filter_space(upsample2(u_coarse, z_sel.shape[1], z_sel.shape[2]))
     if selector == "luma" and z_sel.shape[0] == 3:
         return luma(z_sel)
     if selector not in ("rgb", "luma"):
@@ -311,13 +343,14 @@ def add_phase(s: np.ndarray, phases: int) -> np.ndarray:
 
 
 def select(z_sel: np.ndarray, q_theta: int, t_s, t_c, return_margin: bool = False, selector: str = "rgb",
-           phases: int = 1):
+           phases: int = 1, u_coarse: Optional[np.ndarray] = None):
     """Filter selector s(i) from the image the structure tensor is taken on.
 
     Colour images: z_sel is RGB (the channels summed in Eq. (6)), or its luma with
-    selector="luma"; grey: one channel. phases = 4: phase-aware buckets (add_phase).
+    selector="luma"; grey: one channel. selector="coarse": the upsampled coarser output
+    u_coarse instead (selector_image). phases = 4: phase-aware buckets (add_phase).
     """
-    a, b, c = structure_tensor(selector_image(z_sel, selector))
+    a, b, c = structure_tensor(selector_image(z_sel, selector, u_coarse))
     theta, strength, coh = eigen_features(a, b, c)
     s = add_phase(quantize(theta, strength, coh, q_theta, t_s, t_c), phases)
     if return_margin:
@@ -347,7 +380,7 @@ class LevelBank:
     radius_g: int
     radius_f: Optional[int]
     coeffs: np.ndarray
-    selector: str = "rgb"          # "rgb" (Eq. (6) over R, G, B) or "luma"
+    selector: str = "rgb"          # "rgb" (Eq. (6) over R, G, B), "luma" or "coarse" (selector_image)
     phases: int = 1                # 1, or 4 phase-aware buckets (add_phase); coeffs then has 4K rows
 
     @property
@@ -419,7 +452,7 @@ def denoise(img: np.ndarray, bank: Bank, storage=None, return_index_maps: bool =
     maps = [None] * L
     for lev in range(L - 1, -1, -1):
         lb = bank.levels[lev]
-        s = select(pyr[lev], lb.q_theta, lb.t_s, lb.t_c, selector=lb.selector, phases=lb.phases)
+        s = select(pyr[lev], lb.q_theta, lb.t_s, lb.t_c, selector=lb.selector, phases=lb.phases, u_coarse=u)
         maps[lev] = s
         u = apply_level(to_filter_space(pyr[lev]), s, lb, u_coarse=u)
         if lev > 0:
@@ -433,9 +466,9 @@ def denoise(img: np.ndarray, bank: Bank, storage=None, return_index_maps: bool =
 # trained level by level from the second-coarsest level down (Section 4).
 # --------------------------------------------------------------------------------------
 
-def level_features(z_sel: np.ndarray, selector: str = "rgb"):
+def level_features(z_sel: np.ndarray, selector: str = "rgb", u_coarse: Optional[np.ndarray] = None):
     """(strength, coherence) of every pixel, flattened."""
-    a, b, c = structure_tensor(selector_image(z_sel, selector))
+    a, b, c = structure_tensor(selector_image(z_sel, selector, u_coarse))
     _, strength, coh = eigen_features(a, b, c)
     return strength.ravel(), coh.ravel()
 
@@ -642,7 +675,10 @@ def train_single(pairs, q_theta: int, q_s: int, q_c: int, radius: int, lam: floa
     """Single-scale bank (Eq. (1), (7)-(8)) from (noisy, clean) pairs of (C, H, W) images.
 
     augment: train on the eight symmetries of every pair (Section 5).
-    selector: structure tensor of the colour image ("rgb") or of its luma ("luma")."""
+    selector: structure tensor of the colour image ("rgb") or of its luma ("luma"); a single
+    level has no coarser output, so "coarse" is refused."""
+    if selector == "coarse":
+        raise ValueError("a single-scale level has no coarser output to select on")
     if augment:
         pairs = augment_pairs(pairs)
     zs = [np.asarray(z, dtype=np.float64) for z, _ in pairs]
@@ -675,7 +711,8 @@ def train_multiscale(pairs, n_trained_levels: int, q_theta: int, q_s: int, q_c: 
     equal-population quantiles of each level's training features.
     ``augment``: train on the eight symmetries of every pair (Section 5); each
     symmetric copy is a pair of its own, with its own pyramid and cascade.
-    ``selector``: structure tensor of the colour levels ("rgb") or of their luma ("luma").
+    ``selector``: structure tensor of the colour levels ("rgb"), of their luma ("luma"), or of
+    the upsampled coarser output of the pair's own training cascade ("coarse", selector_image).
     ``phases``: 1, or 4 for phase-aware buckets (add_phase).
     """
     if augment:
@@ -692,7 +729,7 @@ def train_multiscale(pairs, n_trained_levels: int, q_theta: int, q_s: int, q_c: 
         if thresholds is not None:
             t_s, t_c = (np.asarray(t, float) for t in thresholds[lev])
         else:
-            feats = [level_features(p[lev], selector) for p in pz]
+            feats = [level_features(p[lev], selector, uhat[i]) for i, p in enumerate(pz)]
             t_s = thresholds_from_features(np.concatenate([f[0] for f in feats]), q_s)
             t_c = thresholds_from_features(np.concatenate([f[1] for f in feats]), q_c)
         K = q_theta * q_s * q_c * phases
@@ -700,7 +737,7 @@ def train_multiscale(pairs, n_trained_levels: int, q_theta: int, q_s: int, q_c: 
         stats = GramStats.zeros(K, C, D)
         smaps = []
         for i in range(len(pairs)):
-            s = select(pz[i][lev], q_theta, t_s, t_c, selector=selector, phases=phases)
+            s = select(pz[i][lev], q_theta, t_s, t_c, selector=selector, phases=phases, u_coarse=uhat[i])
             smaps.append(s)
             accumulate_level(stats, s, to_filter_space(pz[i][lev]), to_filter_space(pu[i][lev]),
                              radius_g, radius_f, uhat[i])

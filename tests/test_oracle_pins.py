@@ -738,3 +738,110 @@ def test_planted_phase_aware_recovery():
     blind, _, _ = O.train_single(pairs, q_theta, 2, 2, r, 0.0, t_s=t_s, t_c=t_c, n_min=9)
     for b in (0, 4):
         assert np.max(np.abs(blind.levels[0].coeffs[b] - planted[4 * b])) > 1e-3
+
+
+# ----------------------------------------------------------------------------- selection on the coarser output
+
+def test_upsample2_impulse_closed_form():
+    """A coarse impulse spreads as the outer product of the linear-interpolation weights
+    (1/4, 3/4, 3/4, 1/4) over fine pixels 2m-1 .. 2m+2; at the first sample the clamp folds the
+    missing 1/4 onto pixel 0 (weights 1, 3/4, 1/4)."""
+    w = np.array([0.25, 0.75, 0.75, 0.25])
+    x = np.zeros((1, 6, 7))
+    x[0, 2, 3] = 1.0
+    u = O.upsample2(x, 12, 14)
+    want = np.zeros((12, 14))
+    want[3:7, 5:9] = np.outer(w, w)
+    assert np.array_equal(u[0], want)
+    x = np.zeros((1, 6, 7))
+    x[0, 0, 0] = 1.0
+    u = O.upsample2(x, 11, 13)                 # odd sizes: ceil(11/2) = 6, ceil(13/2) = 7
+    e = np.array([1.0, 0.75, 0.25])
+    want = np.zeros((11, 13))
+    want[:3, :3] = np.outer(e, e)
+    assert np.array_equal(u[0], want)
+
+
+def test_upsample2_constants_sums_and_ramps():
+    """Constants stay constant; on even sizes every coarse sample hands out total weight 4 (the sum
+    is preserved up to the factor 4); a ramp sampled at the coarse centres 2m + 1/2 (which is what
+    down2 makes of a fine ramp) comes back as the fine ramp away from the edges."""
+    for H, W in [(1, 1), (2, 3), (9, 8), (33, 17)]:
+        x = np.full((2, (H + 1) // 2, (W + 1) // 2), 0.61)
+        assert np.max(np.abs(O.upsample2(x, H, W) - 0.61)) < 1e-15
+    x = np.random.default_rng(8).random((3, 5, 6))
+    assert abs(O.upsample2(x, 10, 12).sum() - 4 * x.sum()) < 1e-12
+    H, W = 40, 48
+    alpha, beta, c0 = 0.013, -0.007, 0.4
+    m_y, m_x = np.mgrid[0:H // 2, 0:W // 2].astype(float)
+    coarse = (c0 + alpha * (2 * m_x + 0.5) + beta * (2 * m_y + 0.5))[None]
+    yy, xx = np.mgrid[0:H, 0:W].astype(float)
+    fine = c0 + alpha * xx + beta * yy
+    inner = (slice(1, H - 1), slice(1, W - 1))
+    assert np.max(np.abs(O.upsample2(coarse, H, W)[0][inner] - fine[inner])) < 1e-15
+    ramp = fine[None]
+    back = O.upsample2(O.down2(ramp), H, W)[0]
+    core = (slice(5, H - 5), slice(5, W - 5))
+    assert np.max(np.abs(back[core] - fine[core])) < 1e-14
+
+
+@pytest.mark.parametrize("k", [(1.0, 0.5, -2.0), (0.3, 1.2, 0.7)])
+def test_coarse_selector_follows_the_coarser_output(k):
+    """The coarse selector reads u^{l+1} (held in YCbCr), upsamples it and takes it back to RGB:
+    with RGB channels that are parallel ramps k_c (alpha, beta) the features at the fine level are
+    those of the fine ramp, coherence 1 and strength |k| |(alpha, beta)|, whatever the noisy level
+    holds. Features taken on the YCbCr channels themselves would weigh the channels differently."""
+    H, W = 24, 28
+    alpha, beta = 0.011, -0.006
+    m_y, m_x = np.mgrid[0:H // 2, 0:W // 2].astype(float)
+    base = alpha * (2 * m_x + 0.5) + beta * (2 * m_y + 0.5)
+    coarse_rgb = np.stack([0.5 + kc * base for kc in k])
+    u_coarse = O.to_filter_space(coarse_rgb)
+    z = np.random.default_rng(3).random((3, H, W))
+    core = (slice(4, H - 4), slice(4, W - 4))
+    a, b, c = O.structure_tensor(O.selector_image(z, "coarse", u_coarse))
+    theta, strength, coh = O.eigen_features(a, b, c)
+    want = np.mod(np.arctan2(beta, alpha) + np.pi / 2, np.pi)
+    d = np.abs(theta[core] - want)
+    assert np.max(np.minimum(d, np.pi - d)) < 1e-7
+    assert np.max(np.abs(strength[core] - np.linalg.norm(k) * np.hypot(alpha, beta))) < 1e-13
+    assert np.min(coh[core]) > 1 - 1e-6
+    _, s_ycc, _ = O.eigen_features(*O.structure_tensor(O.upsample2(u_coarse, H, W)))
+    assert np.max(np.abs(s_ycc[core] - strength[core])) > 1e-4
+    t_s, t_c = [0.5 * float(np.median(strength))], [0.5]
+    s1 = O.select(z, 8, t_s, t_c, selector="coarse", u_coarse=u_coarse)
+    s2 = O.select(np.zeros_like(z), 8, t_s, t_c, selector="coarse", u_coarse=u_coarse)
+    assert np.array_equal(s1, s2)
+    with pytest.raises(ValueError):
+        O.select(z, 8, t_s, t_c, selector="coarse")
+
+
+def test_planted_recovery_with_coarse_selection():
+    """A level whose buckets come from the upsampled coarser output: targets made by planted
+    per-bucket filters (bucket chosen on the coarser input u^{l+1}) are recovered at lambda = 0."""
+    rng = np.random.default_rng(48)
+    q_theta, rf, rg = 2, 1, 1
+    K, D = q_theta * 2, 18
+    planted = rng.normal(0, 0.3, (K, 3, D))
+    pyrs = [O.build_pyramid(rng.uniform(0, 1, (3, 40, 44)), 2) for _ in range(5)]
+    st = np.concatenate([O.level_features(p[0], "coarse", O.to_filter_space(p[1]))[0] for p in pyrs])
+    t_s, t_c = [float(np.median(st))], []
+    lb = O.LevelBank(q_theta, np.array(t_s), np.array(t_c), rg, rf, planted, selector="coarse")
+    stats = O.GramStats.zeros(K, 3, D)
+    for pz in pyrs:
+        uc = O.to_filter_space(pz[1])
+        s = O.select(pz[0], q_theta, t_s, t_c, selector="coarse", u_coarse=uc)
+        assert 0 < np.mean(s % 2) < 1                    # both strength bins occur
+        target = O.apply_level(O.to_filter_space(pz[0]), s, lb, uc)
+        O.accumulate_level(stats, s, O.to_filter_space(pz[0]), target, rg, rf, uc)
+    h, fb = O.solve_level(stats, 0.0)
+    assert not fb.any()
+    assert np.max(np.abs(h - planted)) < 1e-9
+    # the cascade selects level 0 on its own coarser output
+    bank = O.Bank([lb, O.LevelBank(q_theta, np.array(t_s), np.array(t_c), rg, rf, planted)])
+    img = pyrs[0][0]
+    _, maps = O.denoise(img, bank, return_index_maps=True)
+    pyr = O.build_pyramid(img, 3)
+    u1 = O.apply_level(O.to_filter_space(pyr[1]), maps[1], bank.levels[1], O.to_filter_space(pyr[2]))
+    assert np.array_equal(maps[0], O.select(img, q_theta, t_s, t_c, selector="coarse", u_coarse=u1))
+    assert not np.array_equal(maps[0], O.select(img, q_theta, t_s, t_c))
