@@ -52,7 +52,7 @@ typedef enum { MDN_GRAY = 0, MDN_RGB = 1, MDN_YCC = 2 } mdn_color;
 /* Image the structure tensor of the filter selector is taken on (Section 3): the colour image,
  * its channels summed as in Eq. (6) (the paper's choice), or its luma alone. Grey images are
  * their own luma. */
-typedef enum { MDN_SELECT_RGB = 0, MDN_SELECT_LUMA = 1 } mdn_selector;
+typedef enum { MDN_SELECT_RGB = 0, MDN_SELECT_LUMA = 1, MDN_SELECT_COARSE = 2 } mdn_selector;
 
 typedef struct {
     void*   data;         /* device pointer */
@@ -76,6 +76,12 @@ typedef struct {
  * gradients averaged over a 5x5 box (Eq. (6)); it is evaluated in float64. With
  * selector = MDN_SELECT_LUMA it is taken on the BT.601 luma Y = 0.299 R + 0.587 G + 0.114 B of a
  * colour level instead (float64; the luma-only analysis Section 3 compares against, Fig. 2).
+ * With selector = MDN_SELECT_COARSE (multiscale levels only) it is taken on the coarser level's
+ * output u^{l+1} instead of the noisy z^l: u^{l+1} is upsampled onto this level's grid by linear
+ * interpolation on the pyramid's alignment (coarse sample m lies between fine pixels 2m and 2m+1,
+ * so fine 2m takes 3/4 of m and 1/4 of m-1, fine 2m+1 takes 3/4 of m and 1/4 of m+1, indices
+ * clamped; rows, then columns) and taken back to RGB (float64). This is the alternative to the
+ * noisy input that Eq. (9) leaves open: less noise, half the resolution.
  * coeffs[k][c] holds taps_f = (2*radius_f+1)^2 upscale taps applied to the coarser output at
  * floor(i/2) + j, then taps_g = (2*radius_g+1)^2 taps applied to this level's input at i + j,
  * both row-major over (dy, dx).
@@ -91,7 +97,7 @@ typedef struct {
     int32_t radius_g;     /* 1, 2 or 3 */
     int32_t channels;     /* 1 or 3, must match the images */
     int32_t coeff_dtype;  /* mdn_dtype of coeffs */
-    int32_t selector;     /* mdn_selector: MDN_SELECT_RGB (0) or MDN_SELECT_LUMA (1) */
+    int32_t selector;     /* mdn_selector: MDN_SELECT_RGB (0), MDN_SELECT_LUMA (1) or MDN_SELECT_COARSE (2) */
     int32_t phases;       /* 1, or 4: phase-aware buckets (see above); coeffs then has 4K rows */
     int32_t reserved;     /* must be 0 */
     const double* t_s;    /* HOST, q_s-1 ascending strength thresholds */
@@ -130,6 +136,13 @@ mdn_status mdn_dihedral(const mdn_image* in, int32_t transform, const mdn_image*
  * K <= 256 and uint16 when K > 256 (the paper's 16 x 16 x 16 buckets, Section 5). */
 mdn_status mdn_select_filters(const mdn_image* z, const mdn_level* lvl, void* s_out,
                               int64_t s_pitch, void* stream);
+
+/* Filter selector of a level that selects on the coarser output (MDN_SELECT_COARSE, see mdn_level),
+ * for a width x height level: u_coarse is the coarser output u^{l+1} (YCbCr, or RGB at the coarsest
+ * pyramid level, or grey), ceil(width/2) x ceil(height/2). s_out as for mdn_select_filters. Levels
+ * with another selector return MDN_EINVAL (and mdn_select_filters refuses coarse-selector levels). */
+mdn_status mdn_select_filters_coarse(const mdn_image* u_coarse, int32_t width, int32_t height,
+                                     const mdn_level* lvl, void* s_out, int64_t s_pitch, void* stream);
 
 /* One filtering step (Eq. (1) or Eq. (9)).
  * z:        this level's noisy input, RGB or grey (colour images are converted to YCbCr for
@@ -231,6 +244,12 @@ mdn_status mdn_train_solve(const mdn_gram* g, double lambda, int64_t min_count, 
 mdn_status mdn_level_features(const mdn_image* z, int32_t selector, double* strength, double* coherence,
                               void* stream);
 
+/* The same features for the coarse selector: the structure tensor of u_coarse (ceil(width/2) x
+ * ceil(height/2); YCbCr, RGB or grey) upsampled onto the width x height grid as for
+ * MDN_SELECT_COARSE. Dense [height][width] device arrays. */
+mdn_status mdn_level_features_coarse(const mdn_image* u_coarse, int32_t width, int32_t height, double* strength,
+                                     double* coherence, void* stream);
+
 /* Equal-population thresholds: the k/q quantiles (k = 1..q-1, linear interpolation between order
  * statistics) of n device doubles, written to out_host[q-1]. Synchronises `stream`. */
 mdn_status mdn_quantiles_workspace_size(int64_t n, size_t* bytes);
@@ -243,7 +262,8 @@ mdn_status mdn_quantiles(const double* values, int64_t n, int32_t q, double* out
  * --------------------------------------------------------------------------------------- */
 typedef struct mdn_plan mdn_plan;
 
-/* Create a plan for a float16 7x7/7x7 colour bank (K <= 243 per level). The plan copies the
+/* Create a plan for a float16 7x7/7x7 colour bank (K <= 243 per level, every level selecting on
+ * its own input: coarse-selector levels return MDN_ENOTSUP, as do phase-aware ones). The plan copies the
  * level descriptors and thresholds (the coefficient buffers must stay valid while it is used),
  * creates its own stream, and allocates its device workspace and tables on first use: creation
  * and the first batch of a new size are the only calls that allocate. storage: pyramid dtype. */
@@ -284,7 +304,7 @@ typedef struct mdn_server mdn_server;
 typedef enum { MDN_EXEC_HIP = 0, MDN_EXEC_FAKE = 1 } mdn_executor_kind;
 
 typedef struct mdn_server_config {
-    const mdn_bank* banks;        /* n_banks float16 7x7/7x7 colour banks (K <= 243 per level); the
+    const mdn_bank* banks;        /* n_banks float16 7x7/7x7 colour banks (K <= 243 per level, each level selecting on its own input); the
                                      descriptors and thresholds are copied, the coefficient buffers
                                      must stay valid while the server lives */
     int32_t n_banks;              /* 1..16 */

@@ -2,7 +2,7 @@
 (arXiv 1802.06130): HIP kernels behind the C ABI in include/mdn.h, bound here with ctypes."""
 
 from ._lib import (  # noqa: F401
-    F16, F32, GRAY, RGB, YCC, SELECT_LUMA, SELECT_RGB,
+    F16, F32, GRAY, RGB, YCC, SELECT_COARSE, SELECT_LUMA, SELECT_RGB,
     Bank, Level, MdnError,
     apply_level, denoise, denoise_workspace_size, header_functions, image, lib,
     pyramid_build, select_filters, selector_dtype, dihedral, augment_pairs,

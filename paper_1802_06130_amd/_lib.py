@@ -21,7 +21,7 @@ HEADER_PATH = os.path.join(os.path.dirname(_PKG), "include", "mdn.h")
 MDN_OK, MDN_EINVAL, MDN_ENOMEM, MDN_EDEVICE, MDN_ENOTSUP, MDN_ETIMEOUT, MDN_ECANCELED = range(7)
 F32, F16 = 0, 1
 GRAY, RGB, YCC = 0, 1, 2
-SELECT_RGB, SELECT_LUMA = 0, 1       # mdn_selector
+SELECT_RGB, SELECT_LUMA, SELECT_COARSE = 0, 1, 2       # mdn_selector
 _STATUS = {1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ENOTSUP", 5: "ETIMEOUT", 6: "ECANCELED"}
 
 
@@ -66,6 +66,7 @@ def lib() -> ct.CDLL:
             "mdn_pyramid_build": [P(MdnImage), i32, P(MdnImage), vp],
             "mdn_dihedral": [P(MdnImage), i32, P(MdnImage), vp],
             "mdn_select_filters": [P(MdnImage), P(MdnLevel), vp, i64, vp],
+            "mdn_select_filters_coarse": [P(MdnImage), i32, i32, P(MdnLevel), vp, i64, vp],
             "mdn_apply_level": [P(MdnImage), P(MdnImage), vp, i64, P(MdnLevel), P(MdnImage), vp, vp],
             "mdn_denoise_workspace_size": [i32, i32, i32, i32, i32, P(ct.c_size_t)],
             "mdn_denoise": [P(MdnImage), P(MdnBank), i32, vp, ct.c_size_t, P(MdnImage), vp],
@@ -129,7 +130,7 @@ class Level:
     def __init__(self, q_theta: int, t_s: Sequence[float], t_c: Sequence[float], radius_g: int,
                  radius_f: Optional[int], coeffs, channels: int, selector: int = 0, phases: int = 1):
         self.q_theta = int(q_theta)
-        self.selector = int(selector)          # SELECT_RGB or SELECT_LUMA
+        self.selector = int(selector)          # SELECT_RGB, SELECT_LUMA or SELECT_COARSE
         self.phases = int(phases)              # 1, or 4 phase-aware buckets
         self.t_s = np.ascontiguousarray(np.asarray(t_s, dtype=np.float64))
         self.t_c = np.ascontiguousarray(np.asarray(t_c, dtype=np.float64))
@@ -207,16 +208,24 @@ def _check_map(t, level: Level, name: str):
         raise MdnError(MDN_EINVAL, f"{name}: selector maps of a {level.K}-bucket level are {selector_dtype(level)}")
 
 
-def select_filters(z, level: Level, out=None):
-    """(H, W) bucket map of the RGB/grey image z (uint8, or uint16 when K > 256)."""
+def select_filters(z, level: Level, out=None, u_coarse=None, coarse_color=None):
+    """(H, W) bucket map of the RGB/grey image z (uint8, or uint16 when K > 256). A level with
+    selector=SELECT_COARSE selects on the coarser output u_coarse instead (YCbCr unless coarse_color
+    says otherwise); z then only gives the size."""
     torch = _torch()
     C, H, W = z.shape
     if out is None:
         out = torch.empty((H, W), dtype=selector_dtype(level), device=z.device)
     _check_map(out, level, "out")
     lv = level.desc()
-    _check(lib().mdn_select_filters(ct.byref(image(z)), ct.byref(lv), ct.c_void_p(out.data_ptr()),
-                                    out.stride(0) if H > 0 else W, _stream_ptr()))
+    pitch = out.stride(0) if H > 0 else W
+    if level.selector == SELECT_COARSE and u_coarse is not None:
+        uc = image(u_coarse, coarse_color if coarse_color is not None else (GRAY if C == 1 else YCC))
+        _check(lib().mdn_select_filters_coarse(ct.byref(uc), W, H, ct.byref(lv), ct.c_void_p(out.data_ptr()),
+                                               pitch, _stream_ptr()))
+        return out
+    _check(lib().mdn_select_filters(ct.byref(image(z)), ct.byref(lv), ct.c_void_p(out.data_ptr()), pitch,
+                                    _stream_ptr()))
     return out
 
 
@@ -292,6 +301,7 @@ def _train_sigs(L):
         "mdn_train_solve_workspace_size": [P(MdnGram), P(ct.c_size_t)],
         "mdn_train_solve": [P(MdnGram), ct.c_double, i64, vp, i32, vp, vp, ct.c_size_t, vp],
         "mdn_level_features": [P(MdnImage), i32, vp, vp, vp],
+        "mdn_level_features_coarse": [P(MdnImage), i32, i32, vp, vp, vp],
         "mdn_quantiles_workspace_size": [i64, P(ct.c_size_t)],
         "mdn_quantiles": [vp, i64, i32, P(ct.c_double), vp, ct.c_size_t, vp],
     }
@@ -368,14 +378,22 @@ def train_solve(gram: Gram, lam: float, min_count: Optional[int] = None, coeff_d
     return out, int(nfb.item())
 
 
-def level_features(z, selector: int = 0):
+def level_features(z, selector: int = 0, u_coarse=None, coarse_color=None):
     """(strength, coherence) float64 device tensors [H][W] of the RGB/grey image z (structure tensor
-    of the colour image, or of its luma with selector=SELECT_LUMA)."""
+    of the colour image, of its luma with selector=SELECT_LUMA, or of the upsampled coarser output
+    u_coarse with selector=SELECT_COARSE, YCbCr unless coarse_color says otherwise)."""
     torch = _torch()
     _train_sigs(lib())
     C, H, W = z.shape
     st = torch.empty((H, W), dtype=torch.float64, device=z.device)
     co = torch.empty((H, W), dtype=torch.float64, device=z.device)
+    if selector == SELECT_COARSE:
+        if u_coarse is None:
+            raise MdnError(MDN_EINVAL, "the coarse selector needs u_coarse")
+        uc = image(u_coarse, coarse_color if coarse_color is not None else (GRAY if C == 1 else YCC))
+        _check(lib().mdn_level_features_coarse(ct.byref(uc), W, H, ct.c_void_p(st.data_ptr()),
+                                               ct.c_void_p(co.data_ptr()), _stream_ptr()))
+        return st, co
     _check(lib().mdn_level_features(ct.byref(image(z)), int(selector), ct.c_void_p(st.data_ptr()),
                                     ct.c_void_p(co.data_ptr()), _stream_ptr()))
     return st, co
@@ -395,10 +413,12 @@ def quantiles(values, q: int) -> np.ndarray:
     return np.array(list(out))
 
 
-def level_thresholds(zs, q_s: int, q_c: int, selector: int = 0):
-    """Equal-population strength / coherence thresholds over the given level images."""
+def level_thresholds(zs, q_s: int, q_c: int, selector: int = 0, u_coarse=None, coarse_color=None):
+    """Equal-population strength / coherence thresholds over the given level images (for the
+    coarse selector, over the upsampled coarser outputs u_coarse[i] of the same levels)."""
     torch = _torch()
-    feats = [level_features(z, selector) for z in zs]
+    ucs = u_coarse if u_coarse is not None else [None] * len(zs)
+    feats = [level_features(z, selector, uc, coarse_color) for z, uc in zip(zs, ucs)]
     st = torch.cat([f[0].view(-1) for f in feats])
     co = torch.cat([f[1].view(-1) for f in feats])
     t_s = quantiles(st, q_s) if q_s > 1 else np.zeros(0)
@@ -437,8 +457,8 @@ def train_multiscale(pairs, n_trained_levels: int, q_theta: int, q_s: int, q_c: 
     """Multiscale bank trained from the second-coarsest level down (Section 4); pairs are
     (noisy, clean) (C, H, W) device tensors. Returns (Bank, grams, fallback counts).
     augment: train on the eight symmetries of every pair (Section 5), each its own pair;
-    selector: SELECT_RGB (colour structure tensor) or SELECT_LUMA; phases: 1 or 4 (phase-aware
-    buckets)."""
+    selector: SELECT_RGB (colour structure tensor), SELECT_LUMA or SELECT_COARSE (the upsampled
+    coarser output of the pair's own training cascade); phases: 1 or 4 (phase-aware buckets)."""
     torch = _torch()
     if augment:
         pairs = augment_pairs(pairs)
@@ -457,7 +477,7 @@ def train_multiscale(pairs, n_trained_levels: int, q_theta: int, q_s: int, q_c: 
         if thresholds is not None:
             t_s, t_c = thresholds[lev]
         else:
-            t_s, t_c = level_thresholds([p[lev] for p in pz], q_s, q_c, selector)
+            t_s, t_c = level_thresholds([p[lev] for p in pz], q_s, q_c, selector, uhat, coarse_color)
         K = q_theta * (len(t_s) + 1) * (len(t_c) + 1) * phases
         sel = Level(q_theta, t_s, t_c, radius_g, radius_f, torch.zeros((K, C, D), dtype=torch.float32, device=dev), C,
                     selector, phases)

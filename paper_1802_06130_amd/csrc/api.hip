@@ -63,8 +63,10 @@ mdn_status check_image(const mdn_image* im, const char* name) {
 
 mdn_status check_level(const mdn_level* lv, int channels) {
     if (!lv) return fail(MDN_EINVAL, "level: null");
-    if (lv->selector != MDN_SELECT_RGB && lv->selector != MDN_SELECT_LUMA)
-        return fail(MDN_EINVAL, "level: selector must be MDN_SELECT_RGB or MDN_SELECT_LUMA");
+    if (lv->selector != MDN_SELECT_RGB && lv->selector != MDN_SELECT_LUMA && lv->selector != MDN_SELECT_COARSE)
+        return fail(MDN_EINVAL, "level: selector must be MDN_SELECT_RGB, MDN_SELECT_LUMA or MDN_SELECT_COARSE");
+    if (lv->selector == MDN_SELECT_COARSE && lv->radius_f < 1)
+        return fail(MDN_EINVAL, "level: a single-scale level has no coarser output to select on");
     if (lv->q_theta < 2 || lv->q_theta > kMaxTheta || (lv->q_theta & 1))
         return fail(MDN_EINVAL, "level: q_theta must be even in [2, %d]", kMaxTheta);
     if (lv->q_s < 1 || lv->q_s > kMaxThr || lv->q_c < 1 || lv->q_c > kMaxThr)
@@ -191,10 +193,44 @@ mdn_status mdn_select_filters(const mdn_image* z, const mdn_level* lvl, void* s_
     if (st) return st;
     if (z->color == MDN_YCC) return fail(MDN_EINVAL, "z: the selector reads RGB or grey images");
     if ((st = check_level(lvl, z->channels))) return st;
+    if (lvl->selector == MDN_SELECT_COARSE)
+        return fail(MDN_EINVAL, "level selects on the coarser output: use mdn_select_filters_coarse");
     if (empty(*z)) return MDN_OK;
     if (!s_out) return fail(MDN_EINVAL, "null s_out");
     if (s_pitch < z->width) return fail(MDN_EINVAL, "s_pitch < width");
     return launch_select_apply(*z, nullptr, nullptr, s_pitch, s_out, *lvl, nullptr, static_cast<hipStream_t>(stream));
+}
+
+// The fine level's size, as an image without data (the coarse selector reads only u_coarse).
+static mdn_status coarse_target(const mdn_image* u_coarse, int32_t width, int32_t height, mdn_image* z) {
+    mdn_status st = check_image(u_coarse, "u_coarse");
+    if (st) return st;
+    if (width < 0 || height < 0) return fail(MDN_EINVAL, "negative size");
+    if (u_coarse->width != half_up(width) || u_coarse->height != half_up(height))
+        return fail(MDN_EINVAL, "u_coarse must be ceil(width/2) x ceil(height/2)");
+    memset(z, 0, sizeof(*z));
+    z->width = width;
+    z->height = height;
+    z->channels = u_coarse->channels;
+    z->dtype = MDN_F32;
+    z->color = u_coarse->channels == 3 ? MDN_RGB : MDN_GRAY;
+    z->row_pitch = width;
+    z->plane_pitch = (int64_t)width * height;
+    return MDN_OK;
+}
+
+mdn_status mdn_select_filters_coarse(const mdn_image* u_coarse, int32_t width, int32_t height, const mdn_level* lvl,
+                                     void* s_out, int64_t s_pitch, void* stream) {
+    g_err[0] = 0;
+    mdn_image z;
+    mdn_status st = coarse_target(u_coarse, width, height, &z);
+    if (st) return st;
+    if ((st = check_level(lvl, u_coarse->channels))) return st;
+    if (lvl->selector != MDN_SELECT_COARSE) return fail(MDN_EINVAL, "level does not select on the coarser output");
+    if (width == 0 || height == 0) return MDN_OK;
+    if (!s_out) return fail(MDN_EINVAL, "null s_out");
+    if (s_pitch < width) return fail(MDN_EINVAL, "s_pitch < width");
+    return launch_select_apply(z, u_coarse, nullptr, s_pitch, s_out, *lvl, nullptr, static_cast<hipStream_t>(stream));
 }
 
 mdn_status mdn_apply_level(const mdn_image* z, const mdn_image* u_coarse, const void* s, int64_t s_pitch,
@@ -353,6 +389,8 @@ mdn_status mdn_train_accumulate(const mdn_gram* g, const mdn_image* z, const mdn
     if (z->channels != g->channels) return fail(MDN_EINVAL, "gram channels differ from the image's");
     if ((st = check_level(sel, z->channels))) return st;
     if (level_buckets(*sel) != g->K) return fail(MDN_EINVAL, "selector K differs from gram K");
+    if (sel->selector == MDN_SELECT_COARSE && g->radius_f < 1)
+        return fail(MDN_EINVAL, "the coarse selector needs a layout with the coarser output");
     if (precision != MDN_GRAM_F32 && precision != MDN_GRAM_BF16X3) return fail(MDN_EINVAL, "unknown precision");
     if (g->radius_f >= 1) {
         if ((st = check_image(u_coarse, "u_coarse"))) return st;
@@ -403,12 +441,26 @@ mdn_status mdn_level_features(const mdn_image* z, int32_t selector, double* stre
     g_err[0] = 0;
     mdn_status st = check_image(z, "z");
     if (st) return st;
+    if (selector == MDN_SELECT_COARSE)
+        return fail(MDN_EINVAL, "features of the coarser output: use mdn_level_features_coarse");
     if (selector != MDN_SELECT_RGB && selector != MDN_SELECT_LUMA)
         return fail(MDN_EINVAL, "selector must be MDN_SELECT_RGB or MDN_SELECT_LUMA");
     if (z->color == MDN_YCC) return fail(MDN_EINVAL, "z: pass RGB or grey");
     if (empty(*z)) return MDN_OK;
     if (!strength || !coherence) return fail(MDN_EINVAL, "null output");
-    return launch_features(*z, selector == MDN_SELECT_LUMA, strength, coherence, static_cast<hipStream_t>(stream));
+    return launch_features(*z, selector == MDN_SELECT_LUMA, nullptr, strength, coherence,
+                           static_cast<hipStream_t>(stream));
+}
+
+mdn_status mdn_level_features_coarse(const mdn_image* u_coarse, int32_t width, int32_t height, double* strength,
+                                     double* coherence, void* stream) {
+    g_err[0] = 0;
+    mdn_image z;
+    mdn_status st = coarse_target(u_coarse, width, height, &z);
+    if (st) return st;
+    if (width == 0 || height == 0) return MDN_OK;
+    if (!strength || !coherence) return fail(MDN_EINVAL, "null output");
+    return launch_features(z, 0, u_coarse, strength, coherence, static_cast<hipStream_t>(stream));
 }
 
 mdn_status mdn_quantiles_workspace_size(int64_t n, size_t* bytes) {

@@ -375,6 +375,8 @@ mdn_status mdn_plan_create(const mdn_bank* bank, int32_t storage, int32_t max_im
         if (st) return st;
         if (lv.coeff_dtype != MDN_F16 || !walk_supported(lv, 3))
             return fail(MDN_ENOTSUP, "plan: the batched form runs float16 7x7/7x7 colour banks (K <= 243)");
+        if (lv.selector == MDN_SELECT_COARSE)
+            return fail(MDN_ENOTSUP, "plan: the batched form selects on each level's own input");
     }
     mdn_status ist = init_walk_kernels();
     if (ist) return ist;

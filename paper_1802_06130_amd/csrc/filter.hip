@@ -11,6 +11,10 @@
 //     binned into s(i). The orientation bin is found without atan2: the doubled-angle vector of
 //     the minor eigenvector, (c - a, -2b), is tested against the bin-boundary unit vectors with
 //     cross products.
+//     Levels that select on the coarser output (MDN_SELECT_COARSE) stage that level's window instead,
+//     in float64 and taken back to RGB, and form the gradients of its linear factor-two upsampling
+//     onto this level's grid (fine pixel 2m: 3/4 of coarse m and 1/4 of m-1; 2m+1: 3/4 of m and 1/4
+//     of m+1; rows, then columns), evaluated where the gradient stencil needs it.
 //  3. Filtering, in float32: the staged window is converted to YCbCr in place, the coarser level's
 //     window (for Eq. (9)) is staged too, and every pixel accumulates its bucket's f taps over the
 //     coarse window at floor(i/2) + j and g taps over the fine window at i + j, per channel. The
@@ -32,6 +36,10 @@ constexpr int kZW = kTW + 2 * kHalo;         // 70
 constexpr int kZH = kTH + 2 * kHalo;         // 22
 constexpr int kPW = kTW + 4;                 // tensor-product field: tile + 2-pixel halo
 constexpr int kPH = kTH + 4;
+// Coarse window of the coarse selector: the gradient stencil reads fine pixels y0-3 .. y0+kTH+2,
+// whose interpolation reads coarse rows y0/2-3 .. y0/2+kTH/2+2 (likewise for columns).
+constexpr int kCH = kTH / 2 + 6;             // 14
+constexpr int kCW = kTW / 2 + 6;             // 38
 
 struct FilterArgs {
     ImageArg z;                 // RGB or grey input of this level
@@ -49,8 +57,20 @@ struct FilterArgs {
     int32_t K;
     double* feat_s;             // features mode: strength and coherence per pixel (row pitch W)
     double* feat_c;
+    ImageArg su;                // coarse selector: the coarser output whose upsampling is analysed
+    int32_t su_dtype, su_ycc;
     SelectArg sel;
 };
+
+// YCbCr -> RGB in float64 (the exact algebraic inverse of the BT.601 matrix).
+__device__ __forceinline__ void ycc_to_rgb_d(double& c0, double& c1, double& c2) {
+    const double y = c0, cb = c1 - 0.5, cr = c2 - 0.5;
+    const double r = y + 1.402 * cr;
+    const double b = y + 1.772 * cb;
+    c0 = r;
+    c1 = (y - kLumaR * r - kLumaB * b) / kLumaG;
+    c2 = b;
+}
 
 __device__ __forceinline__ float load_any(const void* base, int32_t dtype, int64_t off) {
     return dtype == MDN_F16 ? __half2float(static_cast<const __half*>(base)[off])
@@ -105,7 +125,8 @@ __device__ __forceinline__ int bucket_of(double a, double b, double c, const Sel
 }
 
 // MODE 0: selector only; 1: selector + filtering; 2: strength/coherence features only.
-template <int C, int RF, int RG, typename TC, int MODE>
+// SU: the structure tensor is taken on the upsampled coarser output (a.su) instead of a.z.
+template <int C, int RF, int RG, typename TC, int MODE, bool SU>
 __global__ __launch_bounds__(256) void k_select_apply(FilterArgs a) {
     constexpr bool APPLY = MODE == 1;
     constexpr int kUH = kTH / 2 + 2 * (RF > 0 ? RF : 0);
@@ -117,20 +138,41 @@ __global__ __launch_bounds__(256) void k_select_apply(FilterArgs a) {
     __shared__ float zs[C][kZH][kZW + 1];
     __shared__ double pa[kPH][kPW], pb[kPH][kPW], pc[kPH][kPW];
     __shared__ float us[C][RF >= 0 ? kUH : 1][RF >= 0 ? kUW + 1 : 1];
+    __shared__ double ucs[SU ? C : 1][SU ? kCH : 1][SU ? kCW : 1];
 
     const int tid = threadIdx.x;
     const int tx = tid & 63, ty = tid >> 6;
     const int x0 = blockIdx.x * kTW, y0 = blockIdx.y * kTH;
     const int W = a.z.w, H = a.z.h;
 
-    // 1. stage the input window (clamped)
-    for (int i = tid; i < C * kZH * kZW; i += 256) {
-        const int c = i / (kZH * kZW);
-        const int rem = i - c * kZH * kZW;
-        const int r = rem / kZW, q = rem - r * kZW;
-        const int gy = clampi(y0 - kHalo + r, 0, H - 1);
-        const int gx = clampi(x0 - kHalo + q, 0, W - 1);
-        zs[c][r][q] = load_any(a.z.data, a.z_dtype, (int64_t)c * a.z.plane + (int64_t)gy * a.z.row + gx);
+    // 1. stage the input window (clamped); the coarse selector without filtering never reads it
+    if constexpr (!SU || APPLY) {
+        for (int i = tid; i < C * kZH * kZW; i += 256) {
+            const int c = i / (kZH * kZW);
+            const int rem = i - c * kZH * kZW;
+            const int r = rem / kZW, q = rem - r * kZW;
+            const int gy = clampi(y0 - kHalo + r, 0, H - 1);
+            const int gx = clampi(x0 - kHalo + q, 0, W - 1);
+            zs[c][r][q] = load_any(a.z.data, a.z_dtype, (int64_t)c * a.z.plane + (int64_t)gy * a.z.row + gx);
+        }
+    }
+    const int cy0 = (y0 >> 1) - 3, cx0 = (x0 >> 1) - 3;
+    if constexpr (SU) {
+        // the coarser output's window, float64 RGB (or grey), at clamped coarse positions
+        for (int i = tid; i < kCH * kCW; i += 256) {
+            const int r = i / kCW, q = i - r * kCW;
+            const int gy = clampi(cy0 + r, 0, a.su.h - 1);
+            const int gx = clampi(cx0 + q, 0, a.su.w - 1);
+            const int64_t off = (int64_t)gy * a.su.row + gx;
+            double v[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) v[c] = (double)load_any(a.su.data, a.su_dtype, off + (int64_t)c * a.su.plane);
+            if constexpr (C == 3) {
+                if (a.su_ycc) ycc_to_rgb_d(v[0], v[1], v[2]);
+            }
+#pragma unroll
+            for (int c = 0; c < C; ++c) ucs[c][r][q] = v[c];
+        }
     }
     __syncthreads();
 
@@ -147,7 +189,29 @@ __global__ __launch_bounds__(256) void k_select_apply(FilterArgs a) {
             const int lyd = clampi(yc + 1, 0, H - 1) - (y0 - kHalo);
             const int lyu = clampi(yc - 1, 0, H - 1) - (y0 - kHalo);
             double A = 0.0, B = 0.0, Cc = 0.0;
-            if (C == 3 && a.sel.luma) {
+            if constexpr (SU) {
+                // linear factor-two upsampling of the coarse window at fine (fy, fx), both clamped
+                const int Hc = a.su.h, Wc = a.su.w;
+                auto up = [&](int c, int fy, int fx) {
+                    const int my = fy >> 1, mx = fx >> 1;
+                    const int ny = (fy & 1) ? min(my + 1, Hc - 1) : max(my - 1, 0);
+                    const int nx = (fx & 1) ? min(mx + 1, Wc - 1) : max(mx - 1, 0);
+                    const int ly = my - cy0, lny = ny - cy0, lx = mx - cx0, lnx = nx - cx0;
+                    const double r0 = 0.75 * ucs[c][ly][lx] + 0.25 * ucs[c][lny][lx];
+                    const double r1 = 0.75 * ucs[c][ly][lnx] + 0.25 * ucs[c][lny][lnx];
+                    return 0.75 * r0 + 0.25 * r1;
+                };
+                const int xr = clampi(xc + 1, 0, W - 1), xl = clampi(xc - 1, 0, W - 1);
+                const int yd = clampi(yc + 1, 0, H - 1), yu = clampi(yc - 1, 0, H - 1);
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    const double gx = (up(c, yc, xr) - up(c, yc, xl)) * 0.5;
+                    const double gy = (up(c, yd, xc) - up(c, yu, xc)) * 0.5;
+                    A += gx * gx;
+                    B += gx * gy;
+                    Cc += gy * gy;
+                }
+            } else if (C == 3 && a.sel.luma) {
                 // luma-only structure tensor: gradients of Y at the four neighbours
                 auto Y = [&](int yy, int xx) { return luma_d(zs[0][yy][xx], zs[1][yy][xx], zs[C - 1][yy][xx]); };
                 const double gx = (Y(ly, lxr) - Y(ly, lxl)) * 0.5;
@@ -323,19 +387,30 @@ __global__ __launch_bounds__(256) void k_select_apply(FilterArgs a) {
 }
 
 template <int C, int RF, int RG, typename TC>
-mdn_status launch_kernel(const FilterArgs& fa, bool apply, int w, int h, hipStream_t st) {
+mdn_status launch_kernel(const FilterArgs& fa, bool apply, bool su, int w, int h, hipStream_t st) {
     dim3 grid((w + kTW - 1) / kTW, (h + kTH - 1) / kTH);
+    if constexpr (RF >= 1) {
+        if (su && apply) {
+            k_select_apply<C, RF, RG, TC, 1, true><<<grid, 256, 0, st>>>(fa);
+            return check_launch("select_apply (coarse selector)");
+        }
+    }
+    if (su) {
+        if (apply) return fail(MDN_EINVAL, "the coarse selector needs a multiscale level");
+        k_select_apply<C, 1, 1, float, 0, true><<<grid, 256, 0, st>>>(fa);
+        return check_launch("select (coarse selector)");
+    }
     if (apply)
-        k_select_apply<C, RF, RG, TC, 1><<<grid, 256, 0, st>>>(fa);
+        k_select_apply<C, RF, RG, TC, 1, false><<<grid, 256, 0, st>>>(fa);
     else
-        k_select_apply<C, RF, RG, TC, 0><<<grid, 256, 0, st>>>(fa);
+        k_select_apply<C, RF, RG, TC, 0, false><<<grid, 256, 0, st>>>(fa);
     return check_launch(apply ? "select_apply" : "select");
 }
 
 template <int C, typename TC>
-mdn_status dispatch_radii(const FilterArgs& fa, bool apply, int rf, int rg, int w, int h, hipStream_t st) {
+mdn_status dispatch_radii(const FilterArgs& fa, bool apply, bool su, int rf, int rg, int w, int h, hipStream_t st) {
 #define MDN_RADII(RF_, RG_) \
-    if (rf == RF_ && rg == RG_) return launch_kernel<C, RF_, RG_, TC>(fa, apply, w, h, st);
+    if (rf == RF_ && rg == RG_) return launch_kernel<C, RF_, RG_, TC>(fa, apply, su, w, h, st);
     MDN_RADII(-1, 1)
     MDN_RADII(-1, 2)
     MDN_RADII(-1, 3)
@@ -350,23 +425,37 @@ mdn_status dispatch_radii(const FilterArgs& fa, bool apply, int rf, int rg, int 
 
 }  // namespace
 
-mdn_status launch_features(const mdn_image& z, int luma, double* strength, double* coherence, hipStream_t st) {
+void set_coarse_source(FilterArgs& fa, const mdn_image& uc) {
+    fa.su = ImageArg{uc.data, uc.row_pitch, uc.plane_pitch, uc.width, uc.height};
+    fa.su_dtype = uc.dtype;
+    fa.su_ycc = uc.color == MDN_YCC;
+}
+
+mdn_status launch_features(const mdn_image& z, int luma, const mdn_image* su, double* strength, double* coherence,
+                           hipStream_t st) {
     if (z.width == 0 || z.height == 0) return MDN_OK;
     FilterArgs fa;
     memset(&fa, 0, sizeof(fa));
     fa.sel.luma = luma && z.channels == 3;
     fa.z = ImageArg{z.data, z.row_pitch, z.plane_pitch, z.width, z.height};
     fa.z_dtype = z.dtype;
+    if (su) set_coarse_source(fa, *su);
     fa.feat_s = strength;
     fa.feat_c = coherence;
     fa.sel.q_theta = 2;
     fa.sel.q_s = 1;
     fa.sel.q_c = 1;
     dim3 grid((z.width + kTW - 1) / kTW, (z.height + kTH - 1) / kTH);
-    if (z.channels == 3)
-        k_select_apply<3, -1, 1, float, 2><<<grid, 256, 0, st>>>(fa);
-    else
-        k_select_apply<1, -1, 1, float, 2><<<grid, 256, 0, st>>>(fa);
+    if (su) {
+        if (z.channels == 3)
+            k_select_apply<3, -1, 1, float, 2, true><<<grid, 256, 0, st>>>(fa);
+        else
+            k_select_apply<1, -1, 1, float, 2, true><<<grid, 256, 0, st>>>(fa);
+    } else if (z.channels == 3) {
+        k_select_apply<3, -1, 1, float, 2, false><<<grid, 256, 0, st>>>(fa);
+    } else {
+        k_select_apply<1, -1, 1, float, 2, false><<<grid, 256, 0, st>>>(fa);
+    }
     return check_launch("features");
 }
 
@@ -407,8 +496,10 @@ void orientation_boundaries(int q_theta, double* bcos, double* bsin) {
 mdn_status launch_select_apply(const mdn_image& z, const mdn_image* uc, const void* s_in, int64_t s_pitch,
                                void* s_out, const mdn_level& lvl, const mdn_image* out, hipStream_t st) {
     if (z.width == 0 || z.height == 0) return MDN_OK;
-    // selector only: column-walk float64 selection pass
-    if (!out && s_out && !s_in) return launch_select_walk(z, lvl, s_out, s_pitch, st);
+    const bool su = lvl.selector == MDN_SELECT_COARSE;
+    if (su && !uc) return fail(MDN_EINVAL, "a level that selects on the coarser output needs u_coarse");
+    // selector only: column-walk float64 selection pass (the coarse selector runs the tiled kernel)
+    if (!out && s_out && !s_in && !su) return launch_select_walk(z, lvl, s_out, s_pitch, st);
     // float16 filter banks of 7x7/7x7 colour filters run on the persistent column-walk kernel
     if (out && uc && lvl.coeff_dtype == MDN_F16 && walk_supported(lvl, z.channels)) {
         if (!s_in && !s_out) return fail(MDN_EINVAL, "float16 levels need a selector map (s) or a buffer for it (s_out)");
@@ -437,13 +528,16 @@ mdn_status launch_select_apply(const mdn_image& z, const mdn_image* uc, const vo
     fa.coeffs = lvl.coeffs;
     fa.K = level_buckets(lvl);
     fill_select_arg(lvl, fa.sel);
+    if (su) set_coarse_source(fa, *uc);
     const bool apply = out != nullptr;
+    const bool su_sel = su && !s_in;        // a given map leaves nothing to select
     const int C = z.channels;
     const int rf = lvl.radius_f < 0 ? -1 : lvl.radius_f;
-    if (C == 3 && lvl.coeff_dtype == MDN_F32) return dispatch_radii<3, float>(fa, apply, rf, lvl.radius_g, z.width, z.height, st);
-    if (C == 3 && lvl.coeff_dtype == MDN_F16) return dispatch_radii<3, __half>(fa, apply, rf, lvl.radius_g, z.width, z.height, st);
-    if (C == 1 && lvl.coeff_dtype == MDN_F32) return dispatch_radii<1, float>(fa, apply, rf, lvl.radius_g, z.width, z.height, st);
-    if (C == 1 && lvl.coeff_dtype == MDN_F16) return dispatch_radii<1, __half>(fa, apply, rf, lvl.radius_g, z.width, z.height, st);
+    const int rg = lvl.radius_g;
+    if (C == 3 && lvl.coeff_dtype == MDN_F32) return dispatch_radii<3, float>(fa, apply, su_sel, rf, rg, z.width, z.height, st);
+    if (C == 3 && lvl.coeff_dtype == MDN_F16) return dispatch_radii<3, __half>(fa, apply, su_sel, rf, rg, z.width, z.height, st);
+    if (C == 1 && lvl.coeff_dtype == MDN_F32) return dispatch_radii<1, float>(fa, apply, su_sel, rf, rg, z.width, z.height, st);
+    if (C == 1 && lvl.coeff_dtype == MDN_F16) return dispatch_radii<1, __half>(fa, apply, su_sel, rf, rg, z.width, z.height, st);
     return fail(MDN_EINVAL, "unsupported channels/coeff dtype");
 }
 

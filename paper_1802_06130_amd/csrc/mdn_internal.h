@@ -104,6 +104,8 @@ inline mdn_status launch_down2(const mdn_image& in, const mdn_image& out, hipStr
 // Selector maps hold uint8 when K <= 256 and uint16 otherwise (s_pitch in elements).
 inline int level_buckets(const mdn_level& lvl) { return lvl.q_theta * lvl.q_s * lvl.q_c * lvl.phases; }
 inline bool wide_selector(const mdn_level& lvl) { return level_buckets(lvl) > 256; }
+// uc: the coarser output, read by the Eq. (9) upscale taps and by levels that select on it
+// (MDN_SELECT_COARSE; with them a selector-only call needs only z's size).
 mdn_status launch_select_apply(const mdn_image& z, const mdn_image* uc, const void* s_in,
                                int64_t s_pitch, void* s_out, const mdn_level& lvl,
                                const mdn_image* out, hipStream_t st);
@@ -113,7 +115,9 @@ mdn_status launch_walk(const mdn_image& z, const mdn_image& uc, const mdn_level&
                        const uint8_t* s_in, uint8_t* s_buf, int64_t s_pitch, hipStream_t st);
 mdn_status launch_select_walk(const mdn_image& z, const mdn_level& lvl, void* s, int64_t s_pitch, hipStream_t st);
 mdn_status launch_dihedral(const mdn_image& in, const mdn_image& out, int t, hipStream_t st);
-mdn_status launch_features(const mdn_image& z, int luma, double* strength, double* coherence, hipStream_t st);
+// su: select on the upsampled coarser output su instead of z (z then only gives the size)
+mdn_status launch_features(const mdn_image& z, int luma, const mdn_image* su, double* strength, double* coherence,
+                           hipStream_t st);
 
 // training
 int gram_dims(const mdn_gram& g, int* D, int* nrhs, int* sys_per_k);

@@ -845,6 +845,8 @@ mdn_status mdn_server_create(const mdn_server_config* cfg, mdn_server** out) {
             if (e) return e;
             if (lv.coeff_dtype != MDN_F16 || !walk_supported(lv, 3))
                 return fail(MDN_ENOTSUP, "server: banks must be float16 7x7/7x7 colour banks (K <= 243)");
+            if (lv.selector == MDN_SELECT_COARSE)
+                return fail(MDN_ENOTSUP, "server: banks must select on each level's own input");
             B.lv[l] = lv;
             for (int j = 0; j < lv.q_s - 1; ++j) B.thr[l][0][j] = lv.t_s[j];
             for (int j = 0; j < lv.q_c - 1; ++j) B.thr[l][1][j] = lv.t_c[j];

@@ -601,7 +601,7 @@ mdn_status train_accumulate(const mdn_gram& g, const mdn_image& z, const mdn_ima
     if ((s = launch_to_planes(z, fine, W, (int64_t)W * H, st))) return s;
     if ((s = launch_to_planes(target, tgt, W, (int64_t)W * H, st))) return s;
     if (uc && (s = launch_to_planes(*uc, coarse, Wc, (int64_t)Wc * Hc, st))) return s;
-    if ((s = launch_select_apply(z, nullptr, nullptr, W, smap, sel, nullptr, st))) return s;
+    if ((s = launch_select_apply(z, uc, nullptr, W, smap, sel, nullptr, st))) return s;
     const int64_t npx = (int64_t)W * H;
     k_iota<<<256, 256, 0, st>>>(idx_in, npx);
     if ((s = check_launch("iota"))) return s;

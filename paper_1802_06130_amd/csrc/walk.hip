@@ -384,7 +384,7 @@ mdn_status launch_walk(const mdn_image& z, const mdn_image& uc, const mdn_level&
     mdn_status e;
     const uint8_t* smap = s_in;
     if (!smap) {
-        if ((e = launch_select_apply(z, nullptr, nullptr, s_pitch, s_buf, lvl, nullptr, st))) return e;
+        if ((e = launch_select_apply(z, &uc, nullptr, s_pitch, s_buf, lvl, nullptr, st))) return e;
         smap = s_buf;
     }
     WalkArgs a;

@@ -44,7 +44,7 @@ def gpu_level(lb: O.LevelBank, channels: int, coeff_dtype=None, device="cuda"):
     import paper_1802_06130_amd as M
     dt = coeff_dtype or torch.float32
     co = torch.tensor(np.ascontiguousarray(lb.coeffs), dtype=torch.float64).to(dt).to(device)
-    sel = M.SELECT_LUMA if lb.selector == "luma" else M.SELECT_RGB
+    sel = {"rgb": M.SELECT_RGB, "luma": M.SELECT_LUMA, "coarse": M.SELECT_COARSE}[lb.selector]
     return M.Level(lb.q_theta, lb.t_s, lb.t_c, lb.radius_g, lb.radius_f, co, channels, sel, lb.phases)
 
 
@@ -53,13 +53,14 @@ def gpu_bank(bank: O.Bank, channels: int, coeff_dtype=None, device="cuda"):
     return M.Bank([gpu_level(lb, channels, coeff_dtype, device) for lb in bank.levels])
 
 
-def index_parity(s_gpu: np.ndarray, z_level: np.ndarray, lb: O.LevelBank):
+def index_parity(s_gpu: np.ndarray, z_level: np.ndarray, lb: O.LevelBank, u_coarse=None):
     """Compare a GPU bucket map with the oracle's; every mismatch must be near a boundary.
+    u_coarse: the coarser output (filter colour space, float64) for coarse-selector levels.
 
     Returns (mismatch mask, number of mismatches, number of near-boundary pixels).
     """
     s_ref, margin = O.select(np.asarray(z_level, np.float64), lb.q_theta, lb.t_s, lb.t_c, return_margin=True,
-                             selector=lb.selector, phases=lb.phases)
+                             selector=lb.selector, phases=lb.phases, u_coarse=u_coarse)
     mism = s_gpu.astype(np.int64) != s_ref
     near = margin < NEAR
     bad = mism & ~near
@@ -85,3 +86,23 @@ def max_abs(a, b, mask=None):
     if mask is not None:
         d = d[..., ~mask]
     return float(d.max()) if d.size else 0.0
+
+
+def check_gram(g, st, tol):
+    """GPU normal equations against the oracle's: counts exact; G, b, yy within the accumulation
+    bound |dG_pq| <= tol sqrt(G_pp G_qq) (Cauchy-Schwarz bound on sum |x_p x_q|). Returns the worst
+    ratio to the bound."""
+    K, C, D, _ = st.G.shape
+    G = g.G.cpu().numpy().reshape(K, C, D, D)
+    b = g.b.cpu().numpy().reshape(K, C, D)
+    n = g.n.cpu().numpy()
+    yy = g.yy.cpu().numpy().reshape(K, C)
+    assert np.array_equal(n, st.n), "sample counts differ"
+    diag = np.sqrt(np.maximum(np.einsum("kcii->kci", st.G), 0.0))
+    bound = tol * diag[:, :, :, None] * diag[:, :, None, :] + 1e-12
+    rel = np.abs(G - st.G) / bound
+    assert rel.max() <= 1.0, f"G outside bound (worst ratio {rel.max():.3g})"
+    yd = np.sqrt(np.maximum(st.yy, 0.0))
+    assert np.all(np.abs(b - st.b) <= tol * diag * yd[:, :, None] + 1e-12)
+    assert np.all(np.abs(yy - st.yy) <= tol * st.yy + 1e-12)
+    return float(rel.max())

@@ -69,7 +69,9 @@ def _level(**kw):
     (_img(data=0x1000), _level(radius_g=4), "radius_g"),
     (_img(data=0x1000), _level(channels=1), "channels"),
     (_img(data=0x1000), _level(coeffs=None), "coeffs"),
-    (_img(data=0x1000), _level(selector=2), "selector"),
+    (_img(data=0x1000), _level(selector=3), "selector"),
+    (_img(data=0x1000), _level(selector=2), "mdn_select_filters_coarse"),
+    (_img(data=0x1000), _level(selector=2, radius_f=-1), "single-scale"),
     (_img(data=0x1000), _level(phases=2), "phases"),
     (B.MdnImage(0x1000, 8, 8, 3, M.F32, M.RGB, 0, 8, 1 << 28), _level(), "2 GiB"),
 ])
@@ -130,3 +132,31 @@ def test_dihedral_rejects_bad_arguments(t, out_wh, alias, msg):
     st = M.lib().mdn_dihedral(ct.byref(src), t, ct.byref(dst), None)
     assert st == B.MDN_EINVAL
     assert msg in M.lib().mdn_last_error().decode()
+
+
+def test_coarse_selector_argument_checks():
+    """The coarse selector's own calls: the level must select on the coarser output, which must be
+    ceil(width/2) x ceil(height/2); the noisy-input calls send such levels to them."""
+    lib = M.lib()
+    B._train_sigs(lib)
+    uc = _img(data=0x3000, w=4, h=4, color=M.YCC)
+    smap = ct.c_void_p(0x2000)
+    st = lib.mdn_select_filters_coarse(ct.byref(uc), 8, 8, ct.byref(_level()), smap, 8, None)
+    assert st == B.MDN_EINVAL and b"does not select on the coarser output" in lib.mdn_last_error()
+    st = lib.mdn_select_filters_coarse(ct.byref(uc), 10, 8, ct.byref(_level(selector=2)), smap, 10, None)
+    assert st == B.MDN_EINVAL and b"ceil(width/2)" in lib.mdn_last_error()
+    st = lib.mdn_select_filters_coarse(ct.byref(uc), 7, 8, ct.byref(_level(selector=2)), smap, 6, None)
+    assert st == B.MDN_EINVAL and b"s_pitch" in lib.mdn_last_error()
+    st = lib.mdn_select_filters_coarse(ct.byref(uc), 0, 0, ct.byref(_level(selector=2)), smap, 0, None)
+    assert st == B.MDN_EINVAL                                  # 0 x 0 needs a 0 x 0 coarser output
+    st = lib.mdn_level_features(ct.byref(_img(data=0x1000)), 2, ct.c_void_p(0x5000), ct.c_void_p(0x6000), None)
+    assert st == B.MDN_EINVAL and b"mdn_level_features_coarse" in lib.mdn_last_error()
+    st = lib.mdn_level_features_coarse(ct.byref(uc), 7, 7, None, None, None)
+    assert st == B.MDN_EINVAL and b"null output" in lib.mdn_last_error()
+    z = _img(data=0x1000)
+    tgt = _img(data=0x7000)
+    g = B.MdnGram(K=216, channels=3, layout=0, radius_f=-1, radius_g=3, reserved=0, G=0x8000, b=0x9000, n=0xa000,
+                  yy=0xb000)
+    st = lib.mdn_train_accumulate(ct.byref(g), ct.byref(z), None, ct.byref(tgt), ct.byref(_level(selector=2)), 0,
+                                  ct.c_void_p(0xc000), 1 << 30, None)
+    assert st == B.MDN_EINVAL and b"coarser output" in lib.mdn_last_error()

@@ -13,6 +13,7 @@ import pytest
 
 import oracle as O
 import synth
+from mdn_testlib import check_gram as _check_gram
 
 pytestmark = pytest.mark.gpu
 
@@ -38,23 +39,6 @@ def _oracle_single_stats(pairs, q_theta, t_s, t_c, radius):
         s = O.select(z.astype(np.float64), q_theta, t_s, t_c)
         O.accumulate_level(st, s, O.to_filter_space(z), O.to_filter_space(u), radius)
     return st
-
-
-def _check_gram(g, st, tol):
-    K, C, D, _ = st.G.shape
-    G = g.G.cpu().numpy().reshape(K, C, D, D)
-    b = g.b.cpu().numpy().reshape(K, C, D)
-    n = g.n.cpu().numpy()
-    yy = g.yy.cpu().numpy().reshape(K, C)
-    assert np.array_equal(n, st.n), "sample counts differ"
-    diag = np.sqrt(np.maximum(np.einsum("kcii->kci", st.G), 0.0))
-    bound = tol * diag[:, :, :, None] * diag[:, :, None, :] + 1e-12
-    rel = np.abs(G - st.G) / bound
-    assert rel.max() <= 1.0, f"G outside bound (worst ratio {rel.max():.3g})"
-    yd = np.sqrt(np.maximum(st.yy, 0.0))
-    assert np.all(np.abs(b - st.b) <= tol * diag * yd[:, :, None] + 1e-12)
-    assert np.all(np.abs(yy - st.yy) <= tol * st.yy + 1e-12)
-    return float(rel.max())
 
 
 @pytest.mark.parametrize("precision,tol", [(0, 2e-5), (1, 2e-4)])
