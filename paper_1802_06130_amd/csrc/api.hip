@@ -333,9 +333,11 @@ mdn_status mdn_denoise(const mdn_image* in, const mdn_bank* bank, int32_t storag
     const mdn_image* coarse = &zl[L];
     for (int l = L - 1; l >= 0; --l) {
         const mdn_image* dst = l == 0 ? out : &ul[l];
-        const bool walk = bank->level[l].coeff_dtype == MDN_F16 && walk_supported(bank->level[l], C);
-        if ((st = launch_select_apply(zl[l], coarse, nullptr, zl[l].width, walk ? smap : nullptr, bank->level[l], dst,
-                                      s)))
+        // the map buffer holds uint8 maps: it serves the column walk and the LDS-bank kernel
+        const mdn_level& lv = bank->level[l];
+        const bool walk = lv.coeff_dtype == MDN_F16 && walk_supported(lv, C);
+        const bool map = walk || (!wide_selector(lv) && apply_lds_supported(lv, C));
+        if ((st = launch_select_apply(zl[l], coarse, nullptr, zl[l].width, map ? smap : nullptr, lv, dst, s)))
             return st;
         coarse = dst;
     }

@@ -505,6 +505,16 @@ mdn_status launch_select_apply(const mdn_image& z, const mdn_image* uc, const vo
         if (!s_in && !s_out) return fail(MDN_EINVAL, "float16 levels need a selector map (s) or a buffer for it (s_out)");
         return launch_walk(z, *uc, lvl, *out, static_cast<const uint8_t*>(s_in), static_cast<uint8_t*>(s_out), s_pitch, st);
     }
+    // other multiscale banks that fit in LDS one channel at a time: selection pass, then filtering
+    // with the bank in LDS (without a map or a buffer for one, the fused kernel below runs)
+    if (out && uc && (s_in || s_out) && apply_lds_supported(lvl, z.channels)) {
+        if (!s_in) {
+            mdn_status e = launch_select_apply(z, uc, nullptr, s_pitch, s_out, lvl, nullptr, st);
+            if (e) return e;
+            s_in = s_out;
+        }
+        return launch_apply_lds(z, *uc, s_in, s_pitch, lvl, *out, st);
+    }
     FilterArgs fa;
     memset(&fa, 0, sizeof(fa));
     fa.z = ImageArg{z.data, z.row_pitch, z.plane_pitch, z.width, z.height};

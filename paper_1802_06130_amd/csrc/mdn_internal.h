@@ -96,7 +96,6 @@ void fill_select_arg(const mdn_level& lvl, SelectArg& a);
 void orientation_boundaries(int q_theta, double* bcos, double* bsin);
 
 // Launchers (stream work only; arguments already validated).
-mdn_status launch_down2_tiled(const mdn_image& in, const mdn_image& out, hipStream_t st);
 mdn_status launch_down2_walk(const mdn_image& in, const mdn_image& out, hipStream_t st);
 inline mdn_status launch_down2(const mdn_image& in, const mdn_image& out, hipStream_t st) {
     return launch_down2_walk(in, out, st);
@@ -111,6 +110,11 @@ mdn_status launch_select_apply(const mdn_image& z, const mdn_image* uc, const vo
                                const mdn_image* out, hipStream_t st);
 
 bool walk_supported(const mdn_level& lvl, int channels);
+// Multiscale levels whose bank, one channel at a time, fits in LDS beside the tile windows
+// (colour levels; float32 7x7/7x7 banks up to 219 buckets) filter from a selector map with the bank in LDS.
+bool apply_lds_supported(const mdn_level& lvl, int channels);
+mdn_status launch_apply_lds(const mdn_image& z, const mdn_image& uc, const void* s, int64_t s_pitch,
+                            const mdn_level& lvl, const mdn_image& out, hipStream_t st);
 mdn_status launch_walk(const mdn_image& z, const mdn_image& uc, const mdn_level& lvl, const mdn_image& out,
                        const uint8_t* s_in, uint8_t* s_buf, int64_t s_pitch, hipStream_t st);
 mdn_status launch_select_walk(const mdn_image& z, const mdn_level& lvl, void* s, int64_t s_pitch, hipStream_t st);
