@@ -276,6 +276,14 @@ mdn_status mdn_plan_destroy(mdn_plan* plan);
 mdn_status mdn_plan_autotune(mdn_plan* plan, const mdn_image* in, const mdn_image* out, int32_t n,
                              int32_t* rows_out, void* stream);
 
+/* Device time of every launch of this batch: the launches of mdn_denoise_batch, in the same order
+ * and with the same strip heights but without a graph, each started on the idle plan stream between
+ * two HIP events, `reps` times (1..1000); us_out (host float[3*levels]) receives the mean microseconds per
+ * launch of the pyramid, selection and filtering kernels of each level (index 3 l + k). The outputs
+ * are written as by mdn_denoise_batch. Synchronises the plan's stream. */
+mdn_status mdn_plan_kernel_times(mdn_plan* plan, const mdn_image* in, const mdn_image* out, int32_t n,
+                                 int32_t reps, float* us_out, void* stream);
+
 /* Denoise n images (in[i] -> out[i], RGB, equal sizes per pair, one dtype per side). With
  * use_graph != 0 the launches are captured once per batch (same images, sizes and buffers) and
  * replayed afterwards. Ordered after prior work on `stream` and before later work. */

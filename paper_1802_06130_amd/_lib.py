@@ -504,6 +504,7 @@ def _plan_sigs(L):
         "mdn_plan_destroy": [vp],
         "mdn_plan_autotune": [vp, P(MdnImage), P(MdnImage), i32, P(i32), vp],
         "mdn_denoise_batch": [vp, P(MdnImage), P(MdnImage), i32, i32, vp],
+        "mdn_plan_kernel_times": [vp, P(MdnImage), P(MdnImage), i32, i32, P(ct.c_float), vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -534,6 +535,15 @@ class Plan:
         rows = (ct.c_int32 * (3 * self.levels))()
         _check(lib().mdn_plan_autotune(self.handle, a, b, n, rows, _stream_ptr()))
         return [tuple(rows[3 * l:3 * l + 3]) for l in range(self.levels)]
+
+    def kernel_times(self, ins, outs=None, reps: int = 3):
+        """Mean device microseconds per launch of the batch's kernels: a list over levels of
+        (pyramid, selection, filtering), from HIP events on the plan's stream (synchronises)."""
+        outs = outs if outs is not None else [_torch().empty_like(t) for t in ins]
+        n, a, b = self._descs(ins, outs)
+        us = (ct.c_float * (3 * self.levels))()
+        _check(lib().mdn_plan_kernel_times(self.handle, a, b, n, int(reps), us, _stream_ptr()))
+        return [tuple(float(x) for x in us[3 * l:3 * l + 3]) for l in range(self.levels)]
 
     def denoise_batch(self, ins, outs=None, use_graph: bool = True):
         outs = outs if outs is not None else [_torch().empty_like(t) for t in ins]

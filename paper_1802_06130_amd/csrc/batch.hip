@@ -434,8 +434,11 @@ mdn_status mdn_plan_autotune(mdn_plan* p, const mdn_image* in, const mdn_image* 
     hipEvent_t e0, e1;
     hipEventCreate(&e0);
     hipEventCreate(&e1);
+    // one warm-up launch, then one timed launch started on an idle stream: events recorded between
+    // back-to-back launches have been seen to miss part of the second launch
     auto time_it = [&](auto&& fn) -> float {
         fn();
+        hipStreamSynchronize(p->stream);
         hipEventRecord(e0, p->stream);
         fn();
         hipEventRecord(e1, p->stream);
@@ -516,6 +519,68 @@ mdn_status mdn_plan_autotune(mdn_plan* p, const mdn_image* in, const mdn_image* 
     if (hipEventRecord(p->ev_out, p->stream) != hipSuccess || hipStreamWaitEvent(cs, p->ev_out, 0) != hipSuccess)
         return fail(MDN_EDEVICE, "plan: stream ordering failed");
     return check_launch("autotune");
+}
+
+mdn_status mdn_plan_kernel_times(mdn_plan* p, const mdn_image* in, const mdn_image* out, int32_t n, int32_t reps,
+                                 float* us_out, void* stream) {
+    clear_error();
+    if (!p) return fail(MDN_EINVAL, "plan: null");
+    mdn_status st = check_batch(p, in, out, n);
+    if (st) return st;
+    if (reps < 1 || reps > 1000) return fail(MDN_EINVAL, "plan: reps must be 1..1000");
+    if (!us_out) return fail(MDN_EINVAL, "plan: null output");
+    hipStream_t cs = static_cast<hipStream_t>(stream);
+    if (hipEventRecord(p->ev_in, cs) != hipSuccess || hipStreamWaitEvent(p->stream, p->ev_in, 0) != hipSuccess)
+        return fail(MDN_EDEVICE, "plan: stream ordering failed");
+    std::vector<uint64_t> sig = signature(in, out, n);
+    if (!(p->tables_valid && sig == p->sig)) {
+        drop_graph(p);
+        if ((st = prepare(p, in, out, n))) return st;
+        p->sig = sig;
+    }
+    // the launches of one batch in their usual order, each between two events on the plan's stream
+    // and started on an idle stream (events recorded between back-to-back launches have been seen to
+    // miss part of the second launch)
+    const int L = p->L, nk = 3 * L;
+    std::vector<hipEvent_t> ev(2 * (size_t)nk * reps, nullptr);
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            st = fail(MDN_EDEVICE, "plan: event creation failed");
+            break;
+        }
+    auto slot = [&](int r, int l, int k) { return 2 * ((size_t)r * nk + 3 * l + k); };
+    auto timed = [&](size_t i, auto&& fn) -> mdn_status {
+        if (hipEventRecord(ev[i], p->stream) != hipSuccess) return fail(MDN_EDEVICE, "plan: event record failed");
+        mdn_status e = fn();
+        if (e) return e;
+        if (hipEventRecord(ev[i + 1], p->stream) != hipSuccess) return fail(MDN_EDEVICE, "plan: event record failed");
+        if (hipEventSynchronize(ev[i + 1]) != hipSuccess) return fail(MDN_EDEVICE, "plan: event wait failed");
+        return MDN_OK;
+    };
+    for (int r = 0; r < reps && !st; ++r) {
+        for (int l = 0; l < L && !st; ++l) st = timed(slot(r, l, 0), [&] { return run_d2(p, l); });
+        for (int l = L - 1; l >= 0 && !st; --l) {
+            st = timed(slot(r, l, 1), [&] { return run_sel(p, l); });
+            if (!st) st = timed(slot(r, l, 2), [&] { return run_walk(p, l); });
+        }
+    }
+    if (!st && hipEventSynchronize(ev.back()) != hipSuccess) st = fail(MDN_EDEVICE, "plan: event wait failed");
+    for (int l = 0; l < L && !st; ++l)
+        for (int k = 0; k < 3; ++k) {
+            double sum = 0.0;
+            for (int r = 0; r < reps; ++r) {
+                float ms = 0.0f;
+                hipEventElapsedTime(&ms, ev[slot(r, l, k)], ev[slot(r, l, k) + 1]);
+                sum += ms;
+            }
+            us_out[3 * l + k] = (float)(sum * 1e3 / reps);
+        }
+    for (auto& e : ev)
+        if (e) hipEventDestroy(e);
+    if (st) return st;
+    if (hipEventRecord(p->ev_out, p->stream) != hipSuccess || hipStreamWaitEvent(cs, p->ev_out, 0) != hipSuccess)
+        return fail(MDN_EDEVICE, "plan: stream ordering failed");
+    return check_launch("kernel_times");
 }
 
 mdn_status mdn_denoise_batch(mdn_plan* p, const mdn_image* in, const mdn_image* out, int32_t n, int32_t use_graph,

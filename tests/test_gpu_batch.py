@@ -91,3 +91,27 @@ def test_batch_rejects_bad_inputs():
     with pytest.raises(M.MdnError):
         plan.denoise_batch([zs[2]], [torch.empty((3, 5, 5), dtype=torch.float16, device="cuda")])
     plan.close()
+
+
+def test_kernel_times_runs_the_same_launches():
+    """mdn_plan_kernel_times runs the batch's launches one at a time between events: positive times for
+    every kernel and level, outputs equal to the batched form's bit for bit; before and after a graph
+    replay of the same batch."""
+    import torch
+    import paper_1802_06130_amd as M
+    gb, zs = _setup()
+    plan = M.Plan(gb, M.F16, max_images=16)
+    want = [o.cpu().numpy() for o in plan.denoise_batch(zs, use_graph=True)]
+    outs = [torch.full_like(z, -1.0) for z in zs]
+    kt = plan.kernel_times(zs, outs, reps=2)
+    torch.cuda.synchronize()
+    assert len(kt) == len(gb.levels) and all(t > 0.0 for lv in kt for t in lv)
+    for o, w in zip(outs, want):
+        assert np.array_equal(o.cpu().numpy(), w)
+    again = [o.cpu().numpy() for o in plan.denoise_batch(zs, use_graph=True)]
+    for a, w in zip(again, want):
+        assert np.array_equal(a, w)
+    with pytest.raises(M.MdnError) as e:
+        plan.kernel_times(zs, outs, reps=0)
+    assert e.value.status == M.MDN_EINVAL
+    plan.close()
