@@ -123,7 +123,14 @@ __global__ __launch_bounds__(64 * MDN_WALK_WAVES) void k_walk(WalkArgs a) {
     }
     __syncthreads();
 
-    for (int strip = blockIdx.x * kWaves + wave; strip < a.n_strips; strip += gridDim.x * kWaves) {
+    // The block's waves take neighbouring strips. When each wave has many strips to walk (a.sync_rounds)
+    // they move on to their next strips together (a barrier per round): neighbouring strips then read
+    // the cache lines they share at about the same time, and L2 serves the second read. Left to drift
+    // apart over 44 strips each, the waves fetched half as many bytes again from HBM. With a few
+    // strips per wave the barrier's waits cost more time than the drift.
+    for (int base = blockIdx.x * kWaves; base < a.n_strips; base += gridDim.x * kWaves) {
+      const int strip = base + wave;
+      if (strip < a.n_strips) {
         WalkImage im;
         if (a.imgs == nullptr) {
             im = a.single;
@@ -289,6 +296,8 @@ __global__ __launch_bounds__(64 * MDN_WALK_WAVES) void k_walk(WalkArgs a) {
                 if constexpr (I & 1) coarse_row(unext, cw[((I + 1) / 2 + 3) % 7]);
             }, std::make_integer_sequence<int, 14>{});
         }
+      }
+      if (a.sync_rounds) __syncthreads();   // uniform: every wave reaches it once per round
     }
 }
 
@@ -369,6 +378,7 @@ mdn_status launch_walk_args(const WalkArgs& args, int zd, int ud, int od, hipStr
     const int ncu = device_cus();
     const int blocks = (a.n_strips + kWaves - 1) / kWaves;
     const int grid = blocks < ncu ? blocks : ncu;
+    a.sync_rounds = (int64_t)a.n_strips >= 24LL * grid * kWaves;     // 24 or more strips per wave
     const bool zh = zd == MDN_F16, uh = ud == MDN_F16, oh = od == MDN_F16;
     if (zh && uh && oh) return launch_typed_walk<_Float16, _Float16, _Float16>(a, grid, lds, st);
     if (!zh && uh && !oh) return launch_typed_walk<float, _Float16, float>(a, grid, lds, st);

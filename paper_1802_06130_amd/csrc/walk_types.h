@@ -36,6 +36,7 @@ struct WalkArgs {
     const void* coeffs;         // [K][3][98], float16 or float32
     int32_t coeff_dtype, K;
     int32_t bank_stride;        // bytes between buckets in LDS (set by the launcher)
+    int32_t sync_rounds;        // the block's waves start their strips together (set by the launcher)
 };
 
 struct SelImage {
