@@ -115,3 +115,27 @@ def test_kernel_times_runs_the_same_launches():
         plan.kernel_times(zs, outs, reps=0)
     assert e.value.status == M.MDN_EINVAL
     plan.close()
+
+
+def test_batch_with_many_strips_per_wave_equals_per_image():
+    """A batch large enough that the level-0 filtering launch gives every wave 24 or more strips, so
+    the block's waves move on to their strips together (a barrier per round): every output still
+    equals the per-image call, which has a few strips per wave and no such barrier, bit for bit."""
+    import torch
+    import paper_1802_06130_amd as M
+    H, W, n = 3024, 4032, 16
+    bank = trained_bank_multiscale(levels=3)
+    gb = gpu_bank(bank, 3, coeff_dtype=torch.float16)
+    g = torch.Generator(device="cuda").manual_seed(1234)
+    zs = [(torch.rand((3, H, W), generator=g, device="cuda") * 255).round().div(255).half() for _ in range(n)]
+    # level-0 strips of the default heights: 58 columns by walk rows (28 for a 4032 x 3024 image)
+    props = torch.cuda.get_device_properties(0)
+    strips = n * ((W + 57) // 58) * ((H + 27) // 28)
+    assert strips >= 24 * props.multi_processor_count * 8
+    plan = M.Plan(gb, M.F16, max_images=n)
+    outs = plan.denoise_batch(zs, use_graph=True)
+    torch.cuda.synchronize()
+    for i, z in enumerate(zs):
+        want = M.denoise(z, gb, storage=M.F16)
+        assert torch.equal(outs[i], want), f"image {i} differs"
+    plan.close()
