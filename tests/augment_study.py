@@ -10,7 +10,7 @@ paper's training corpus and test set, so the numbers are context, not a reproduc
 Cost: mdn_dihedral on a 4032x3024 float16 RGB frame, all eight symmetries, HIP events; bytes moved
 = read + write of the frame.
 
-Run on a GPU machine:  python tests/augment_study.py  (prints one JSON object)
+Run with an MI355X visible:  python tests/augment_study.py  (prints one JSON object)
 """
 
 import json

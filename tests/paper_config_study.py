@@ -8,7 +8,7 @@ ridge 1e-3, float32 coefficients; PSNR over 8 held-out seeded 512x512 images. Th
 of one seeded 4032x3024 RGB frame, float32 storage (the path that serves banks too large for LDS),
 HIP events, median of 5. Synthetic scenes stand in for the paper's corpus and test set.
 
-Run on a GPU machine:  python tests/paper_config_study.py  (prints one JSON object)
+Run with an MI355X visible:  python tests/paper_config_study.py  (prints one JSON object)
 """
 
 import json

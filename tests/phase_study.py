@@ -7,7 +7,7 @@ float32 throughput.
 images; throughput of mdn_denoise on one seeded 4032x3024 frame, float32 storage and filters, HIP
 events, median of 5. Synthetic scenes stand in for the paper's corpus and test set.
 
-Run on a GPU machine:  python tests/phase_study.py  (prints one JSON object)
+Run with an MI355X visible:  python tests/phase_study.py  (prints one JSON object)
 """
 
 import json

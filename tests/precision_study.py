@@ -8,7 +8,7 @@ arithmetic differs. Reports, per level and precision: the worst Gram entry error
 sqrt(G_pp G_qq), the coefficient error, the output-space error sqrt(sum dh^T G dh / sum y^2)
 and, end to end, the PSNR of a held-out 512x512 image denoised with each bank.
 
-Run on a GPU machine:  python tests/precision_study.py  (prints one JSON object)
+Run with an MI355X visible:  python tests/precision_study.py  (prints one JSON object)
 """
 
 import json

@@ -12,7 +12,7 @@ Cost: the selection pass (mdn_select_filters, or mdn_select_filters_coarse from 
 float16 YCbCr coarser output) on a 4032x3024 float16 RGB frame with each selector, and the whole
 float16 cascade (mdn_denoise, float16 coefficients) with the sigma-25 banks; HIP events, median of 20.
 
-Run on a GPU machine:  python tests/selector_study.py  (prints one JSON object)
+Run with an MI355X visible:  python tests/selector_study.py  (prints one JSON object)
 """
 
 import json
