@@ -128,7 +128,11 @@ __global__ __launch_bounds__(64 * MDN_WALK_WAVES) void k_walk(WalkArgs a) {
     // the cache lines they share at about the same time, and L2 serves the second read. Left to drift
     // apart over 44 strips each, the waves fetched half as many bytes again from HBM. With a few
     // strips per wave the barrier's waits cost more time than the drift.
-    for (int base = blockIdx.x * kWaves; base < a.n_strips; base += gridDim.x * kWaves) {
+    // XCD-aware order: blocks go to the 8 XCDs round-robin; give each XCD a contiguous run of
+    // logical block numbers so that neighbouring strip groups share an L2
+    const int G = gridDim.x, b = blockIdx.x, xq = G / 8, xr = G % 8, xcd = b % 8;
+    const int lb = (xcd < xr ? xcd * (xq + 1) : xr * (xq + 1) + (xcd - xr) * xq) + b / 8;
+    for (int base = lb * kWaves; base < a.n_strips; base += gridDim.x * kWaves) {
       const int strip = base + wave;
       if (strip < a.n_strips) {
         WalkImage im;
