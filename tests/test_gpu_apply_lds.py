@@ -70,6 +70,27 @@ def test_lds_bank_filter_matches_oracle(q, rf, rg, H, W, storage, coarse_rgb):
     assert err <= (TOL_F32 if storage == np.float32 else TOL_F16)
 
 
+@pytest.mark.parametrize("q,rf,rg", [((8, 3, 3), 2, 3), ((16, 2, 2), 2, 2), ((8, 6, 6), 1, 1)])
+@pytest.mark.parametrize("H,W", [(7, 9), (200, 328)])
+def test_lds_bank_float16_coefficients(q, rf, rg, H, W):
+    """Float16 banks of other radii than 7x7/7x7 take the same kernel (their rows are copied to LDS
+    as float32, pairs of taps at a time): exact conversion, so the float32 bar holds."""
+    import paper_1802_06130_amd as M
+    torch = _torch()
+    print(f"lds apply f16 coefficients q={q} rf={rf} rg={rg} {H}x{W}", flush=True)
+    lb = _level(q, rf, rg, seed=7 + H, coeff_dtype=np.float16)
+    K = lb.K
+    z, _ = synth.noisy_pair(60 + W, H, W, 3, 25)
+    uc = O.rgb_to_ycc(synth.noisy_pair(61 + W, (H + 1) // 2, (W + 1) // 2, 3, 10)[0].astype(np.float64))
+    uc = uc.astype(np.float32)
+    s = np.random.default_rng(H).integers(0, K, (H, W)).astype(np.uint16 if K > 256 else np.uint8)
+    out = M.apply_level(_dev(z), gpu_level(lb, 3, coeff_dtype=torch.float16), u_coarse=_dev(uc), s=_dev(s))
+    ref = O.apply_level(O.to_filter_space(z.astype(np.float64)), s.astype(np.int64), lb, u_coarse=uc.astype(np.float64))
+    err = max_abs(_host(out), ref)
+    print(f"  max-abs {err:.3g}")
+    assert err <= TOL_F32
+
+
 def test_lds_bank_selector_outside_the_bank_is_nan():
     import paper_1802_06130_amd as M
     torch = _torch()

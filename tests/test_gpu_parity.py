@@ -117,6 +117,24 @@ def test_single_scale_grey(H, W):
     assert err <= TOL_F32
 
 
+@pytest.mark.parametrize("H,W", [(7, 9), (130, 97), (256, 256)])
+def test_single_scale_rgb(H, W):
+    """Eq. (1) on a colour image: colour structure tensor, YCbCr filtering, RGB output."""
+    import paper_1802_06130_amd as M
+    print(f"single-scale rgb {H}x{W}", flush=True)
+    bank = trained_bank_single(channels=3)
+    z, u = synth.noisy_pair(1003, H, W, 3, 25)
+    out = _host(M.denoise(_dev(z), gpu_bank(bank, 3)))
+    ref = O.denoise(z, bank, storage=np.float32)
+    s = M.select_filters(_dev(z), gpu_level(bank.levels[0], 3)).cpu().numpy()
+    mism, _, _ = index_parity(s, z, bank.levels[0])
+    err = max_abs(out, ref, mism)
+    print(f"  max-abs={err:.3g} excluded={int(mism.sum())}")
+    assert err <= TOL_F32
+    if H * W > 10000:
+        assert O.psnr(out, u) > O.psnr(z, u) + 3
+
+
 def _check_cascade(img, bank, storage=np.float32, tol=TOL_F32, storage_t=None):
     """GPU denoise vs oracle denoise: per-level index parity and output max-abs."""
     import paper_1802_06130_amd as M

@@ -247,6 +247,14 @@ def test_bad_configurations():
     with pytest.raises(M.MdnError) as e:
         _server(banks=[M.Bank([lv])])
     assert e.value.status == M.MDN_ENOTSUP
+    # banks built around the column walks only: levels that select on the coarser output, and
+    # phase-aware levels, are refused
+    co = torch.zeros(216, 3, 98, dtype=torch.float16)
+    for lvx in (M.Level(24, [0.01, 0.02], [0.3, 0.6], 3, 3, co, 3, M.SELECT_COARSE),
+                M.Level(6, [0.01, 0.02], [0.3, 0.6], 3, 3, co, 3, M.SELECT_RGB, 4)):
+        with pytest.raises(M.MdnError) as e:
+            _server(banks=[M.Bank([lvx] * LEVELS)])
+        assert e.value.status == M.MDN_ENOTSUP
     srv = _server()
     with pytest.raises(M.MdnError):
         srv.submit_request(_req(64, 64, bank=3))
