@@ -5,8 +5,10 @@ Paper configuration at noise sigma: 16x16x16 buckets, 7x7 denoise / 5x5 upscale 
 below sigma 10), as many levels as bring the coarsest level's noise below 2 (oracle.paper_setup).
 Both banks are trained on the GPU from 64 seeded 256x256 pairs with the eight symmetries (Section 5),
 ridge 1e-3, float32 coefficients; PSNR over 8 held-out seeded 512x512 images. Throughput: mdn_denoise
-of one seeded 4032x3024 RGB frame, float32 storage (the path that serves banks too large for LDS),
-HIP events, median of 5. Synthetic scenes stand in for the paper's corpus and test set.
+of one seeded 4032x3024 RGB frame, HIP events, median of 5, twice: float32 storage and coefficients,
+and float16 storage and coefficients (the column walk for the 216-bucket bank; the tiled kernel
+with coefficients read through L2 for the 4096-bucket bank). Synthetic scenes stand in for the
+paper's corpus and test set.
 
 Run with an MI355X visible:  python tests/paper_config_study.py  (prints one JSON object)
 """
@@ -24,14 +26,15 @@ import oracle as O  # noqa: E402
 import synth  # noqa: E402
 
 
-def _time_denoise(M, torch, bank, frame):
+def _time_denoise(M, torch, bank, frame, storage=None):
+    storage = M.F32 if storage is None else storage
     out = torch.empty_like(frame)
-    M.denoise(frame, bank, out=out)
+    M.denoise(frame, bank, storage=storage, out=out)
     torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(5)]
     for a, b in ev:
         a.record()
-        M.denoise(frame, bank, out=out)
+        M.denoise(frame, bank, storage=storage, out=out)
         b.record()
     torch.cuda.synchronize()
     return float(np.median([a.elapsed_time(b) for a, b in ev]))
@@ -55,10 +58,14 @@ def main():
             ps = [O.psnr(M.denoise(torch.from_numpy(z).to(dev), bank).cpu().numpy().astype(np.float64), u)
                   for z, u in tests]
             ms = _time_denoise(M, torch, bank, frame)
+            b16 = M.Bank([M.Level(lv.q_theta, lv.t_s, lv.t_c, lv.radius_g, lv.radius_f, lv.coeffs.half(), 3)
+                          for lv in bank.levels])
+            ms16 = _time_denoise(M, torch, b16, frame.half(), M.F16)
             row[name] = {"levels": l_ + 1, "buckets": qt_ * qs_ * qc_, "radius_f": rf_, "radius_g": rg_,
                          "psnr_db": round(float(np.mean(ps)), 4), "fallback_systems": [int(f) for f in fbs],
-                         "frame_ms_f32": round(ms, 3), "MP_s_f32": round(3024 * 4032 / ms * 1e-3, 1)}
-            del bank
+                         "frame_ms_f32": round(ms, 3), "MP_s_f32": round(3024 * 4032 / ms * 1e-3, 1),
+                         "frame_ms_f16": round(ms16, 3), "MP_s_f16": round(3024 * 4032 / ms16 * 1e-3, 1)}
+            del bank, b16
             torch.cuda.empty_cache()
         res[f"sigma_{int(sigma)}"] = row
     print(json.dumps(res))
