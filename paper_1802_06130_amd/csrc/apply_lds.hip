@@ -10,8 +10,10 @@
 //  1. stages the tile's input window (g radius halo, clamped) converted to YCbCr, and the coarser
 //     output's window at floor(i/2) + j (clamped, converted from RGB at the coarsest level);
 //  2. per channel, copies that channel's K rows of D taps (padded to a multiple of four) into LDS
-//     with 8-byte loads, each block starting at another row, and lets every thread accumulate its
-//     eight pixels' f and g taps, reading its bucket's row with 16-byte LDS loads.
+//     with 8-byte loads, each block starting at another row, and lets every thread accumulate the
+//     f and g taps of its eight pixels, consecutive rows of one column: the window rows are read
+//     from LDS once into registers and reused down the column, and each pixel's bucket row comes
+//     in with 16-byte LDS loads.
 // The taps are summed in the order of the tiled kernel (f taps row-major, then g taps, one fused
 // multiply-add each), so for the same selector the two kernels give the same float32 result.
 // Colour levels only: grey multiscale levels keep the tiled kernel.
@@ -105,20 +107,24 @@ __global__ __launch_bounds__(kLThreads, 2) void k_apply_lds(ApplyLdsArgs a) {
         for (int c = 0; c < C; ++c) us[c][r][q] = v[c];
     }
 
-    // 2. the selector of this thread's pixels (rows ty, ty + 8, ..., ty + 56)
+    // 2. the selector of this thread's pixels: rows kLRows * ty .. kLRows * ty + 7 of column tx.
+    //    Vertical neighbours share all but one row of their g window and, in pairs, their whole f
+    //    window, so the window rows are loaded once into registers and reused down the column.
     int sv[kLRows];
 #pragma unroll
     for (int j = 0; j < kLRows; ++j) {
-        const int y = y0 + ty + 8 * j, x = x0 + tx;
+        const int y = y0 + kLRows * ty + j, x = x0 + tx;
         const int64_t o = (int64_t)y * a.s_pitch + x;
         sv[j] = (y < H && x < W) ? (a.s16 ? (int)static_cast<const uint16_t*>(a.s)[o]
                                           : (int)static_cast<const uint8_t*>(a.s)[o])
                                  : 0;
     }
 
+    constexpr int NG = 2 * RG + 1, NF = 2 * RF + 1;
     // per-channel results, indexed by compile-time pixel and channel only (so they stay in registers)
     float acc0[kLRows], acc1[kLRows], acc2[kLRows];
     const int K = a.K;
+    const int py0 = kLRows * ty, px = tx;
 #pragma unroll 1
     for (int c = 0; c < C; ++c) {
         __syncthreads();        // windows staged; the previous channel's rows are no longer read
@@ -147,33 +153,38 @@ __global__ __launch_bounds__(kLThreads, 2) void k_apply_lds(ApplyLdsArgs a) {
             }
         }
         __syncthreads();
+        float gw[kLRows + 2 * RG][NG];          // g window rows py0 .. py0 + 7 + 2 RG (loaded on first use)
+        float fw[kLRows / 2 + 2 * RF][NF];      // f window rows py0/2 .. py0/2 + 3 + 2 RF
 #pragma unroll
         for (int j = 0; j < kLRows; ++j) {
-            const int py = ty + 8 * j, px = tx;
+            // rows entering the windows at this pixel
+#pragma unroll
+            for (int r = (j == 0 ? 0 : j + 2 * RG); r <= j + 2 * RG; ++r)
+#pragma unroll
+                for (int dx = 0; dx < NG; ++dx) gw[r][dx] = zs[c][py0 + r][px + dx];
+            if (j % 2 == 0) {
+#pragma unroll
+                for (int r = (j == 0 ? 0 : j / 2 + 2 * RF); r <= j / 2 + 2 * RF; ++r)
+#pragma unroll
+                    for (int dx = 0; dx < NF; ++dx) fw[r][dx] = us[c][py0 / 2 + r][px / 2 + dx];
+            }
             const int s = sv[j] < K ? sv[j] : 0;       // a selector outside the bank yields NaN below
             const float4* h4 = reinterpret_cast<const float4*>(bank + (size_t)s * S::DP);
-            // all of the pixel's loads first (one wait), then the taps in order
-            float4 q[S::DP / 4];
-#pragma unroll
-            for (int t4 = 0; t4 < S::DP / 4; ++t4) q[t4] = h4[t4];
-            float wv[S::D];
-#pragma unroll
-            for (int t = 0; t < S::D; ++t) {
-                if (t < S::TF) {
-                    const int dy = t / (2 * RF + 1), dx = t - dy * (2 * RF + 1);
-                    wv[t] = us[c][py / 2 + dy][px / 2 + dx];
-                } else {
-                    const int tg = t - S::TF;
-                    const int dy = tg / (2 * RG + 1), dx = tg - dy * (2 * RG + 1);
-                    wv[t] = zs[c][py + dy][px + dx];
-                }
-            }
             float sum = 0.0f;
 #pragma unroll
-            for (int t = 0; t < S::D; ++t) {
-                const float4 qq = q[t >> 2];
-                const float h = (t & 3) == 0 ? qq.x : (t & 3) == 1 ? qq.y : (t & 3) == 2 ? qq.z : qq.w;
-                sum += h * wv[t];
+            for (int t4 = 0; t4 < S::DP / 4; ++t4) {
+                const float4 q = h4[t4];
+                const float qv[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int t = 4 * t4 + e;
+                    if (t < S::TF) {
+                        sum += qv[e] * fw[j / 2 + t / NF][t % NF];
+                    } else if (t < S::D) {
+                        const int tg = t - S::TF;
+                        sum += qv[e] * gw[j + tg / NG][tg % NG];
+                    }
+                }
             }
             if (sv[j] >= K) sum = __builtin_nanf("");
             if (c == 0) acc0[j] = sum;
@@ -185,7 +196,7 @@ __global__ __launch_bounds__(kLThreads, 2) void k_apply_lds(ApplyLdsArgs a) {
     // 3. store (back to RGB at the finest level)
 #pragma unroll
     for (int j = 0; j < kLRows; ++j) {
-        const int y = y0 + ty + 8 * j, x = x0 + tx;
+        const int y = y0 + kLRows * ty + j, x = x0 + tx;
         if (y >= H || x >= W) continue;
         float o[C];
         o[0] = acc0[j];
