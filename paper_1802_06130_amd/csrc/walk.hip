@@ -61,15 +61,6 @@ __device__ __forceinline__ float dot2(uint32_t c, uint32_t w, float acc) {
     return __builtin_amdgcn_fdot2(__builtin_bit_cast(h2, c), __builtin_bit_cast(h2, w), acc, false);
 }
 
-__device__ __forceinline__ float ld(const void* p, int dtype, int64_t off) {
-    return dtype == MDN_F16 ? (float)static_cast<const _Float16*>(p)[off] : static_cast<const float*>(p)[off];
-}
-__device__ __forceinline__ void st(void* p, int dtype, int64_t off, float v) {
-    if (dtype == MDN_F16)
-        static_cast<_Float16*>(p)[off] = (_Float16)v;
-    else
-        static_cast<float*>(p)[off] = v;
-}
 
 template <int I>
 using IC = std::integral_constant<int, I>;
@@ -102,23 +93,41 @@ __global__ __launch_bounds__(64 * MDN_WALK_WAVES) void k_walk(WalkArgs a) {
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);     // wave-uniform
 
     const int bstride = __builtin_amdgcn_readfirstlane(a.bank_stride);
-    // ---- bank into LDS: row (k, c, r) = 7 taps + 0, float16
+    // ---- bank into LDS: row (k, c, r) = 7 taps + 0, float16. One thread takes a whole (bucket,
+    // channel) vector of 98 taps: all of its loads are issued before the first row is packed, so a
+    // launch pays one memory latency for the fill (per-tap loads in a loop paid one per row).
     {
-        const int nrows = a.K * 3 * kRows;
-        for (int i = tid; i < nrows; i += 64 * kWaves) {
-            const int k = i / (3 * kRows);
-            const int rem = i - k * 3 * kRows;
-            const int c = rem / kRows, r = rem - c * kRows;
-            const int64_t base = ((int64_t)k * 3 + c) * 98 + r * 7;
-            float v[7];
-            for (int t = 0; t < 7; ++t) v[t] = ld(a.coeffs, a.coeff_dtype, base + t);
-            // the 7th tap meets the shared pair (x+3 of Y | x+3 of Cb) for Y and Cb, (x+3 of Cr | 0) for Cr
-            u4 q;
-            q.x = pack2(v[0], v[1]);
-            q.y = pack2(v[2], v[3]);
-            q.z = pack2(v[4], v[5]);
-            q.w = c == 1 ? pack2(0.0f, v[6]) : pack2(v[6], 0.0f);
-            *reinterpret_cast<u4*>(bank + (size_t)k * bstride + (size_t)rem * kRowBytes) = q;
+        const int nvec = a.K * 3;
+        for (int i = tid; i < nvec; i += 64 * kWaves) {
+            const int k = i / 3, c = i - 3 * k;
+            float v[98];
+            if (a.coeff_dtype == MDN_F16) {
+                // 98 halves at a 196-byte multiple: 49 aligned words
+                const uint32_t* src = reinterpret_cast<const uint32_t*>(static_cast<const __half*>(a.coeffs)) +
+                                      (int64_t)i * 49;
+                uint32_t w[49];
+#pragma unroll
+                for (int d = 0; d < 49; ++d) w[d] = src[d];
+#pragma unroll
+                for (int d = 0; d < 49; ++d) {
+                    v[2 * d] = __half2float(__ushort_as_half((unsigned short)(w[d] & 0xffffu)));
+                    v[2 * d + 1] = __half2float(__ushort_as_half((unsigned short)(w[d] >> 16)));
+                }
+            } else {
+                const float* src = static_cast<const float*>(a.coeffs) + (int64_t)i * 98;
+#pragma unroll
+                for (int t = 0; t < 98; ++t) v[t] = src[t];
+            }
+#pragma unroll
+            for (int r = 0; r < kRows; ++r) {
+                // the 7th tap meets the shared pair (x+3 of Y | x+3 of Cb) for Y and Cb, (x+3 of Cr | 0) for Cr
+                u4 q;
+                q.x = pack2(v[7 * r], v[7 * r + 1]);
+                q.y = pack2(v[7 * r + 2], v[7 * r + 3]);
+                q.z = pack2(v[7 * r + 4], v[7 * r + 5]);
+                q.w = c == 1 ? pack2(0.0f, v[7 * r + 6]) : pack2(v[7 * r + 6], 0.0f);
+                *reinterpret_cast<u4*>(bank + (size_t)k * bstride + (size_t)(c * kRows + r) * kRowBytes) = q;
+            }
         }
     }
     __syncthreads();
@@ -308,7 +317,9 @@ __global__ __launch_bounds__(64 * MDN_WALK_WAVES) void k_walk(WalkArgs a) {
 }  // namespace
 
 bool walk_supported(const mdn_level& lvl, int channels) {
-    return channels == 3 && lvl.radius_f == 3 && lvl.radius_g == 3 && lvl.phases == 1 && level_buckets(lvl) <= kMaxK;
+    // the bank is copied a word at a time: 4-byte aligned coefficients
+    return channels == 3 && lvl.radius_f == 3 && lvl.radius_g == 3 && lvl.phases == 1 && level_buckets(lvl) <= kMaxK &&
+           ((uintptr_t)lvl.coeffs & 3) == 0;
 }
 
 size_t walk_lds_bytes(int K) { return (size_t)K * bank_stride(K); }
