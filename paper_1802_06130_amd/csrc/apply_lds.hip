@@ -78,7 +78,9 @@ __global__ __launch_bounds__(kLThreads, 2) void k_apply_lds(ApplyLdsArgs a) {
     const int x0 = blockIdx.x * kLTW, y0 = blockIdx.y * kLTH;
     const int W = a.z.w, H = a.z.h;
 
-    // 1. windows: this level's input (YCbCr) and the coarser output, clamped at the borders
+    // 1. windows: this level's input (YCbCr) and the coarser output, clamped at the borders (loop
+    //    unrolled so that several iterations' loads are in flight together)
+#pragma unroll 4
     for (int i = tid; i < S::ZH * S::ZW; i += kLThreads) {
         const int r = i / S::ZW, q = i - r * S::ZW;
         const int gy = clampi(y0 - RG + r, 0, H - 1);
@@ -92,6 +94,7 @@ __global__ __launch_bounds__(kLThreads, 2) void k_apply_lds(ApplyLdsArgs a) {
         for (int c = 0; c < C; ++c) zs[c][r][q] = v[c];
     }
     const int cy0 = y0 / 2 - RF, cx0 = x0 / 2 - RF;
+#pragma unroll 4
     for (int i = tid; i < S::UH * S::UW; i += kLThreads) {
         const int r = i / S::UW, q = i - r * S::UW;
         const int gy = clampi(cy0 + r, 0, a.uc.h - 1);
@@ -136,6 +139,7 @@ __global__ __launch_bounds__(kLThreads, 2) void k_apply_lds(ApplyLdsArgs a) {
         const int rot = (int)((blockIdx.x * 7u + blockIdx.y * 13u) % (unsigned)K) * D2;
         if (a.coeff_dtype == MDN_F16) {
             const __half2* src = static_cast<const __half2*>(a.coeffs);
+#pragma unroll 8
             for (int i = tid; i < n2; i += kLThreads) {
                 int e = i + rot;
                 e = e >= n2 ? e - n2 : e;
@@ -145,6 +149,7 @@ __global__ __launch_bounds__(kLThreads, 2) void k_apply_lds(ApplyLdsArgs a) {
             }
         } else {
             const float2* src = static_cast<const float2*>(a.coeffs);
+#pragma unroll 8
             for (int i = tid; i < n2; i += kLThreads) {
                 int e = i + rot;
                 e = e >= n2 ? e - n2 : e;
