@@ -137,7 +137,12 @@ __global__ __launch_bounds__(256) void k_select_apply(FilterArgs a) {
 
     __shared__ float zs[C][kZH][kZW + 1];
     __shared__ double pa[kPH][kPW], pb[kPH][kPW], pc[kPH][kPW];
-    __shared__ float us[C][RF >= 0 ? kUH : 1][RF >= 0 ? kUW + 1 : 1];
+    // The coarser output's window is staged after the selection has read its last tensor product,
+    // in the storage of pa: the block's LDS then admits three blocks per CU.
+    using UsRows = float[RF >= 0 ? kUH : 1][RF >= 0 ? kUW + 1 : 1];
+    static_assert(sizeof(float) * C * (RF >= 0 ? kUH : 1) * (RF >= 0 ? kUW + 1 : 1) <= sizeof(pa),
+                  "the coarse window fits in the tensor-product field");
+    UsRows* us = reinterpret_cast<UsRows*>(&pa[0][0]);
     __shared__ double ucs[SU ? C : 1][SU ? kCH : 1][SU ? kCW : 1];
 
     const int tid = threadIdx.x;
