@@ -11,6 +11,11 @@ with coefficients read through L2 for the 4096-bucket bank). Synthetic scenes st
 paper's corpus and test set.
 
 Run with an MI355X visible:  python tests/paper_config_study.py  (prints one JSON object)
+
+With --frame SIGMA it only times the cascade of the paper configuration at that noise level on one
+seeded 4032x3024 float16 frame: seeded stand-in coefficients (float16), thresholds at the
+equal-population quantiles of a 1024x1024 crop of the frame, 3 untimed and 5 timed calls. This is
+the command the kernel trace and counters of that configuration are taken on.
 """
 
 import json
@@ -40,7 +45,38 @@ def _time_denoise(M, torch, bank, frame, storage=None):
     return float(np.median([a.elapsed_time(b) for a, b in ev]))
 
 
+def frame_only(sigma):
+    import time
+    import torch
+    import paper_1802_06130_amd as M
+    dev = torch.device("cuda:0")
+    L, rf, rg, (qt, qs, qc) = O.paper_setup(sigma)
+    frame = torch.from_numpy(synth.noisy_pair(7, 3024, 4032, 3, sigma)[0]).to(dev).half()
+    t_s, t_c = M.level_thresholds([frame[:, :1024, :1024].float().contiguous()], qs, qc)
+    K = qt * qs * qc
+    levels = []
+    for lev in range(L):
+        co = synth.random_bank_coeffs(40 + lev, K, 3, (2 * rf + 1) ** 2, (2 * rg + 1) ** 2)
+        levels.append(M.Level(qt, t_s, t_c, rg, rf, torch.from_numpy(co).to(dev).half(), 3))
+    bank = M.Bank(levels)
+    out = torch.empty_like(frame)
+    ws = torch.empty(M.denoise_workspace_size(4032, 3024, 3, L, M.F16), dtype=torch.uint8, device=dev)
+    for _ in range(3):
+        M.denoise(frame, bank, storage=M.F16, ws=ws, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        M.denoise(frame, bank, storage=M.F16, ws=ws, out=out)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / 5 * 1e3
+    print(json.dumps({"sigma": sigma, "levels": L + 1, "buckets": K, "radius_f": rf, "radius_g": rg,
+                      "frame_ms_f16": round(ms, 3), "MP_s_f16": round(3024 * 4032 / ms * 1e-3, 1)}))
+
+
 def main():
+    if len(sys.argv) == 3 and sys.argv[1] == "--frame":
+        frame_only(float(sys.argv[2]))
+        return
     import torch
     import paper_1802_06130_amd as M
     dev = torch.device("cuda:0")
