@@ -233,15 +233,20 @@ def _make_train_pair(args):
     return z, u
 
 
-def run_training(M, torch):
+def run_training(M, torch, n_pairs=TRAIN_PAIRS, pool=True):
     """Training throughput on 256 seeded 512x512 RGB pairs (sigma per pair from {15, 25, 50}/255,
     rng(3)), 3-level pyramid: accumulation of the level-0 normal equations (D = 98 per channel, 67.1 M
-    samples) in both Gram precisions, then the level's FP64 solve (648 systems)."""
+    samples) in both Gram precisions, then the level's FP64 solve (648 systems). The profiler probe
+    takes the first n_pairs of them, generated in this process (pool=False)."""
     rng = np.random.default_rng(3)
-    sig = rng.choice([15.0, 25.0, 50.0], TRAIN_PAIRS)
-    workers = max(1, min(16, len(os.sched_getaffinity(0))))
-    with mp.get_context("fork").Pool(workers) as pool:
-        pairs = pool.map(_make_train_pair, [(1 + i, float(g)) for i, g in enumerate(sig)], chunksize=8)
+    sig = rng.choice([15.0, 25.0, 50.0], TRAIN_PAIRS)[:n_pairs]
+    jobs = [(1 + i, float(g)) for i, g in enumerate(sig)]
+    if pool:
+        workers = max(1, min(16, len(os.sched_getaffinity(0))))
+        with mp.get_context("fork").Pool(workers) as pool_:
+            pairs = pool_.map(_make_train_pair, jobs, chunksize=8)
+    else:
+        pairs = [_make_train_pair(j) for j in jobs]
     dev = torch.device("cuda:0")
     zs = [torch.from_numpy(z).to(dev) for z, _ in pairs]
     us = [torch.from_numpy(u).to(dev) for _, u in pairs]
@@ -251,10 +256,10 @@ def run_training(M, torch):
     K, C, D = Q_THETA * Q_S * Q_C, 3, 98
     sel = M.Level(Q_THETA, t_s, t_c, RADIUS, RADIUS, torch.zeros((K, C, D), device=dev), 3)
     stream = torch.cuda.current_stream()
-    samples = TRAIN_PAIRS * TRAIN_SIZE * TRAIN_SIZE
+    samples = n_pairs * TRAIN_SIZE * TRAIN_SIZE
     useful = 2.0 * (D * D + D) * C * samples          # G and b products per sample and channel
     issued = 2.0 * 128 * 128 * C * samples             # MFMA tiles cover D padded to 128
-    out = {"workload": f"{TRAIN_PAIRS} RGB pairs {TRAIN_SIZE}x{TRAIN_SIZE}, level 0 of a 3-level pyramid, "
+    out = {"workload": f"{n_pairs} RGB pairs {TRAIN_SIZE}x{TRAIN_SIZE}, level 0 of a 3-level pyramid, "
                        f"D = 98 per channel, {K} buckets, {samples / 1e6:.1f} M samples"}
     g = None
     for name, prec, peak, mult in (("fp32_mfma", M.GRAM_F32, FP32_MFMA_PEAK_TFLOPS, 1),
@@ -391,12 +396,19 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f32", action="store_true")
     ap.add_argument("--pmc-probe", action="store_true", help="run only the hardware-counter probe")
+    ap.add_argument("--train-probe", action="store_true",
+                    help="run only the training measurement on 64 pairs, without worker processes (for the profiler)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-train", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2000)
     args = ap.parse_args()
     if args.pmc_probe:
         pmc_probe()
+        return
+    if args.train_probe:
+        import torch
+        import paper_1802_06130_amd as M
+        print(json.dumps(run_training(M, torch, n_pairs=64, pool=False)), flush=True)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU; the library has no multi-GPU path (images are independent "
