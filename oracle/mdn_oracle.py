@@ -430,35 +430,56 @@ def apply_level(z_f: np.ndarray, s: np.ndarray, lb: LevelBank, u_coarse: Optiona
     return out
 
 
-def denoise(img: np.ndarray, bank: Bank, storage=None, return_index_maps: bool = False):
+def _given_map(maps, lev: int, shape) -> Optional[np.ndarray]:
+    """The caller's bucket map of level ``lev`` (None: select as usual)."""
+    if maps is None or maps[lev] is None:
+        return None
+    s = np.asarray(maps[lev]).astype(np.int64)
+    if s.shape != tuple(shape):
+        raise ValueError(f"index map of level {lev} is {s.shape}, the level is {tuple(shape)}")
+    return s
+
+
+def denoise(img: np.ndarray, bank: Bank, storage=None, return_index_maps: bool = False, maps=None):
     """Coarse-to-fine cascade of Section 4: u^L = z^L, then Eq. (9) for l = L-1 .. 0.
 
     With a single level whose filters have no upscale block this is the plain
     single-scale filter of Eq. (1). ``storage`` (None, float32 or float16) rounds
     every stored pyramid level and every intermediate output to that type, to
     mirror a storage precision; arithmetic stays float64.
+
+    ``maps``: optional list, one entry per trained level, of (H_l, W_l) bucket maps that
+    replace the selection of that level (None entries select as usual). A pixel whose
+    features lie on a bucket boundary may legitimately take either bucket; with the maps
+    another implementation actually used, the cascade is then defined for every pixel.
     """
     L = len(bank.levels)
     multiscale = bank.levels[0].radius_f is not None
     img = round_storage(img, storage)
+    if maps is not None and len(maps) != L:
+        raise ValueError(f"maps: one entry per trained level ({L}), got {len(maps)}")
     if not multiscale:
         lb = bank.levels[0]
-        s = select(img, lb.q_theta, lb.t_s, lb.t_c, selector=lb.selector, phases=lb.phases)
+        s = _given_map(maps, 0, img.shape[1:])
+        if s is None:
+            s = select(img, lb.q_theta, lb.t_s, lb.t_c, selector=lb.selector, phases=lb.phases)
         out = from_filter_space(apply_level(to_filter_space(img), s, lb))
         out = round_storage(out, storage)
         return (out, [s]) if return_index_maps else out
     pyr = build_pyramid(img, L + 1, storage)
     u = to_filter_space(pyr[L])
-    maps = [None] * L
+    out_maps = [None] * L
     for lev in range(L - 1, -1, -1):
         lb = bank.levels[lev]
-        s = select(pyr[lev], lb.q_theta, lb.t_s, lb.t_c, selector=lb.selector, phases=lb.phases, u_coarse=u)
-        maps[lev] = s
+        s = _given_map(maps, lev, pyr[lev].shape[1:])
+        if s is None:
+            s = select(pyr[lev], lb.q_theta, lb.t_s, lb.t_c, selector=lb.selector, phases=lb.phases, u_coarse=u)
+        out_maps[lev] = s
         u = apply_level(to_filter_space(pyr[lev]), s, lb, u_coarse=u)
         if lev > 0:
             u = round_storage(u, storage)
     out = round_storage(from_filter_space(u), storage)
-    return (out, maps) if return_index_maps else out
+    return (out, out_maps) if return_index_maps else out
 
 
 # --------------------------------------------------------------------------------------

@@ -845,3 +845,205 @@ def test_planted_recovery_with_coarse_selection():
     u1 = O.apply_level(O.to_filter_space(pyr[1]), maps[1], bank.levels[1], O.to_filter_space(pyr[2]))
     assert np.array_equal(maps[0], O.select(img, q_theta, t_s, t_c, selector="coarse", u_coarse=u1))
     assert not np.array_equal(maps[0], O.select(img, q_theta, t_s, t_c))
+
+
+# ----------------------------------------------------------------------------- training loop (Section 4)
+
+def _planted_level(rng, q_theta, t_s, t_c, rg, rf, K, D):
+    return _bank_level(q_theta, t_s, t_c, rg, rf, rng.normal(0, 0.3, (K, 3, D)))
+
+
+def test_train_multiscale_recovers_a_planted_level():
+    """One trained level through train_multiscale itself: clean images made by a planted level
+    (upscale block on the coarser level z^1 = u^1-hat, denoise block on z^0) are recovered at
+    lambda = 0, whatever the loop does around accumulate and solve."""
+    rng = np.random.default_rng(61)
+    q_theta, rf, rg = 4, 1, 1
+    t_s, t_c = [0.375], []                              # about the median strength of this white noise
+    K, D = q_theta * 2, 18
+    planted = _planted_level(rng, q_theta, t_s, t_c, rg, rf, K, D)
+    pairs = []
+    for _ in range(6):
+        z = rng.uniform(0, 1, (3, 44, 50))
+        pz = O.build_pyramid(z, 2)
+        s0 = O.select(pz[0], q_theta, t_s, t_c)
+        u_ycc = O.apply_level(O.to_filter_space(pz[0]), s0, planted, O.to_filter_space(pz[1]))
+        pairs.append((z, O.ycc_to_rgb(u_ycc)))
+    bank, stats, fb = O.train_multiscale(pairs, 1, q_theta, 2, 1, rf, rg, 0.0, thresholds=[(t_s, t_c)])
+    assert not fb[0].any()
+    assert stats[0].n.min() > 20 * D
+    assert np.max(np.abs(bank.levels[0].coeffs - planted.coeffs)) < 1e-9
+
+
+def test_train_multiscale_feeds_each_level_the_fitted_coarser_output():
+    """Two trained levels: level 1 is fitted on (z^1, u^2-hat = z^2) against u^1, and level 0 on
+    (z^0, the fitted level 1's own output) against u^0; each level's thresholds are the
+    equal-population quantiles of that level's features. Feeding z^1 in place of the fitted output,
+    or the other level's thresholds, fails below."""
+    pairs = [synth.noisy_pair(300 + i, 40, 48, 3, 25) for i in range(3)]
+    pairs = [(z.astype(np.float64), u.astype(np.float64)) for z, u in pairs]
+    q_theta, q_s, q_c, rf, rg = 4, 2, 2, 1, 1
+    bank, stats, _ = O.train_multiscale(pairs, 2, q_theta, q_s, q_c, rf, rg, 1e-3)
+    pz = [O.build_pyramid(z, 3) for z, _ in pairs]
+    pu = [O.build_pyramid(u, 3) for _, u in pairs]
+    # thresholds of level l: the medians (q = 2) of level l's strength and coherence
+    for lev in range(2):
+        feats = [O.level_features(p[lev]) for p in pz]
+        st = np.concatenate([f[0] for f in feats])
+        co = np.concatenate([f[1] for f in feats])
+        assert np.allclose(bank.levels[lev].t_s, [np.median(st)], rtol=0, atol=1e-15)
+        assert np.allclose(bank.levels[lev].t_c, [np.median(co)], rtol=0, atol=1e-15)
+    assert abs(bank.levels[0].t_s[0] - bank.levels[1].t_s[0]) > 1e-3
+    K, D = q_theta * q_s * q_c, 18
+    want1 = O.GramStats.zeros(K, 3, D)
+    want0 = O.GramStats.zeros(K, 3, D)
+    wrong0 = O.GramStats.zeros(K, 3, D)
+    for p, q in zip(pz, pu):
+        lb1, lb0 = bank.levels[1], bank.levels[0]
+        s1 = O.select(p[1], q_theta, lb1.t_s, lb1.t_c)
+        O.accumulate_level(want1, s1, O.to_filter_space(p[1]), O.to_filter_space(q[1]), rg, rf,
+                           O.to_filter_space(p[2]))
+        uh1 = O.apply_level(O.to_filter_space(p[1]), s1, lb1, O.to_filter_space(p[2]))
+        s0 = O.select(p[0], q_theta, lb0.t_s, lb0.t_c)
+        O.accumulate_level(want0, s0, O.to_filter_space(p[0]), O.to_filter_space(q[0]), rg, rf, uh1)
+        O.accumulate_level(wrong0, s0, O.to_filter_space(p[0]), O.to_filter_space(q[0]), rg, rf,
+                           O.to_filter_space(p[1]))
+    for got, want in ((stats[1], want1), (stats[0], want0)):
+        assert np.array_equal(got.n, want.n)
+        scale = np.max(np.abs(want.G))
+        assert np.max(np.abs(got.G - want.G)) <= 1e-12 * scale
+        assert np.max(np.abs(got.b - want.b)) <= 1e-12 * scale
+    assert np.max(np.abs(wrong0.G - want0.G)) > 1e-3 * np.max(np.abs(want0.G))
+
+
+# ----------------------------------------------------------------------------- margins (near-boundary pixels)
+
+def _tensor_from_eigen(theta, lam1, lam2):
+    """[[a, b], [b, c]] with minor eigenvector (cos theta, sin theta) of eigenvalue lam2 and major
+    eigenvector (-sin theta, cos theta) of eigenvalue lam1."""
+    s, c = np.sin(theta), np.cos(theta)
+    return lam1 * s * s + lam2 * c * c, (lam2 - lam1) * s * c, lam1 * c * c + lam2 * s * s
+
+
+def test_select_margins_against_mpmath_distances():
+    """Each margin recomputed in 50-digit arithmetic from its definition: the distance of sqrt(lam1)
+    and of the coherence from the nearest threshold, and the distance of the unit-trace point
+    ((a - c), 2b) / tr from the nearest boundary line, taken as a cross product with the line's
+    direction (cos 2 theta_b, sin 2 theta_b), theta_b = b pi / Q (no angle of the tensor needed)."""
+    import mpmath as mp
+    mp.mp.dps = 50
+    rng = np.random.default_rng(71)
+    n = 300
+    a = rng.uniform(0, 1, n) ** 3
+    c = rng.uniform(0, 1, n) ** 3
+    b = rng.uniform(-1, 1, n) * np.sqrt(a * c)
+    q_theta, t_s, t_c = 24, [0.2, 0.5], [0.1, 0.4, 0.7]
+    th, st, co = O.eigen_features(a, b, c)
+    m = O.select_margins(a, b, c, th, st, co, q_theta, t_s, t_c)
+    for i in range(n):
+        am, bm, cm = mp.mpf(a[i]), mp.mpf(b[i]), mp.mpf(c[i])
+        tr = am + cm
+        mu = mp.sqrt((am - cm) ** 2 + 4 * bm * bm)
+        s1 = mp.sqrt((tr + mu) / 2)
+        s2 = mp.sqrt(max((tr - mu) / 2, mp.mpf(0)))
+        coh = (s1 - s2) / (s1 + s2)
+        ms = min(abs(s1 - t) for t in t_s)
+        mc = min(abs(coh - t) for t in t_c)
+        mo = min(abs((am - cm) * mp.sin(2 * k * mp.pi / q_theta) - 2 * bm * mp.cos(2 * k * mp.pi / q_theta)) / tr
+                 for k in range(q_theta))
+        want = float(min(ms, mc, mo))
+        assert abs(m[i] - want) <= 1e-12 * max(1.0, want) + 1e-14, (i, m[i], want)
+
+
+def test_select_margins_planted_distances():
+    """Features planted at a known distance from one boundary: strength t + 3e-7, coherence
+    t + 5e-7, and an orientation Delta past a bin edge, whose margin is the anisotropy
+    (lam1 - lam2) / (lam1 + lam2) times |sin 2 Delta| (the doubled angle of the tensor)."""
+    q_theta = 16
+    mid = (5 + 0.5) * np.pi / q_theta                 # middle of orientation bin 5
+    # strength: sqrt(lam1) planted 3e-7 above the threshold, coherence far from its thresholds
+    a, b, c = _tensor_from_eigen(mid, 0.09, 0.01)
+    th, st, co = O.eigen_features(np.array([a]), np.array([b]), np.array([c]))
+    m = O.select_margins(np.array([a]), np.array([b]), np.array([c]), th, st, co, q_theta,
+                         [st[0] - 3e-7], [co[0] + 0.2])
+    assert abs(m[0] - 3e-7) < 1e-15
+    m = O.select_margins(np.array([a]), np.array([b]), np.array([c]), th, st, co, q_theta,
+                         [st[0] + 0.2], [co[0] - 5e-7])
+    assert abs(m[0] - 5e-7) < 1e-15
+    # orientation: Delta past the edge of bin 7 (theta_b = 7 pi / 16)
+    for delta in (1e-3, -2e-4, 4e-2):
+        lam1, lam2 = 0.3, 0.05
+        a, b, c = _tensor_from_eigen(7 * np.pi / q_theta + delta, lam1, lam2)
+        th, st, co = O.eigen_features(np.array([a]), np.array([b]), np.array([c]))
+        assert abs(th[0] - (7 * np.pi / q_theta + delta)) < 1e-12
+        m = O.select_margins(np.array([a]), np.array([b]), np.array([c]), th, st, co, q_theta, [10.0], [10.0])
+        want = (lam1 - lam2) / (lam1 + lam2) * abs(np.sin(2 * delta))
+        assert abs(m[0] - want) < 1e-10 * want, (delta, m[0], want)
+    # the margin is a distance: a threshold just inside it never changes the bucket
+    a, b, c = _tensor_from_eigen(mid, 0.09, 0.01)
+    A, B, Cc = np.array([a]), np.array([b]), np.array([c])
+    th, st, co = O.eigen_features(A, B, Cc)
+    for t in (st[0] - 1e-6, st[0] + 1e-6):
+        m = O.select_margins(A, B, Cc, th, st, co, q_theta, [t], [])
+        s_lo = O.quantize(th, st - 0.99 * m, co, q_theta, [t], [])
+        s_hi = O.quantize(th, st + 0.99 * m, co, q_theta, [t], [])
+        assert s_lo[0] == s_hi[0] == O.quantize(th, st, co, q_theta, [t], [])[0]
+
+
+# ----------------------------------------------------------------------------- PSNR (quality measure, Section 5)
+
+def test_psnr_closed_form_and_clip():
+    ref = np.full((3, 8, 8), 0.5)
+    assert abs(O.psnr(ref + 0.1, ref) - 20.0) < 1e-12          # MSE 1e-2 at peak 1
+    assert abs(O.psnr(ref - 0.01, ref) - 40.0) < 1e-12
+    est = ref.copy()
+    est[0] += 0.1                                               # one channel of three: MSE 1e-2 / 3
+    assert abs(O.psnr(est, ref) - 10 * np.log10(300.0)) < 1e-12
+    one = np.ones((1, 4, 4))
+    assert O.psnr(one + 0.7, one) == float("inf")             # clipped to the peak: no error
+    assert abs(O.psnr(-0.5 * one, 0.2 * one) - 20 * np.log10(1 / 0.2)) < 1e-12
+
+
+# ----------------------------------------------------------------------------- cascade at given index maps
+
+def test_denoise_at_given_maps():
+    """The cascade run at given per-level index maps: its own maps change nothing; a different
+    bucket at one level-0 pixel changes that pixel only, to Eq. (9) with that bucket's filters; a
+    different bucket at one level-1 pixel changes level 0 only inside that pixel's cone (coarse taps
+    at floor(i/2) + j, |j| <= radius_f)."""
+    bank = O.Bank([_bank_level(8, [0.03], [0.5], 1, 1, np.random.default_rng(5 + lev).normal(0, 0.2, (32, 3, 18)))
+                   for lev in range(2)])
+    z, _ = synth.noisy_pair(91, 30, 34, 3, 25)
+    z = z.astype(np.float64)
+    out, maps = O.denoise(z, bank, return_index_maps=True)
+    assert np.array_equal(O.denoise(z, bank, maps=maps), out)
+    assert np.array_equal(O.denoise(z, bank, maps=[None, maps[1]]), out)
+    y, x = 13, 21
+    m0 = [maps[0].copy(), maps[1]]
+    m0[0][y, x] = (maps[0][y, x] + 5) % 32
+    alt = O.denoise(z, bank, maps=m0)
+    diff = np.any(alt != out, axis=0)
+    assert diff[y, x] and diff.sum() == 1
+    pyr = O.build_pyramid(z, 3)
+    u2 = O.to_filter_space(pyr[2])
+    u1 = O.apply_level(O.to_filter_space(pyr[1]), maps[1], bank.levels[1], u2)
+    z0 = O.to_filter_space(pyr[0])
+    h = bank.levels[0].coeffs[m0[0][y, x]]
+    pix = np.zeros(3)
+    for ch in range(3):
+        for t, (dy, dx) in enumerate(O.tap_offsets(1)):
+            pix[ch] += h[ch, t] * u1[ch, min(max(y // 2 + dy, 0), 14), min(max(x // 2 + dx, 0), 16)]
+        for t, (dy, dx) in enumerate(O.tap_offsets(1)):
+            pix[ch] += h[ch, 9 + t] * z0[ch, min(max(y + dy, 0), 29), min(max(x + dx, 0), 33)]
+    assert np.max(np.abs(O.ycc_to_rgb(pix[:, None, None])[:, 0, 0] - alt[:, y, x])) < 1e-12
+    yc, xc = 6, 9
+    m1 = [maps[0], maps[1].copy()]
+    m1[1][yc, xc] = (maps[1][yc, xc] + 3) % 32
+    alt = O.denoise(z, bank, maps=m1)
+    diff = np.argwhere(np.any(alt != out, axis=0))
+    assert len(diff) > 0
+    assert np.all(np.abs(diff[:, 0] // 2 - yc) <= 1) and np.all(np.abs(diff[:, 1] // 2 - xc) <= 1)
+    with pytest.raises(ValueError):
+        O.denoise(z, bank, maps=[maps[0]])
+    with pytest.raises(ValueError):
+        O.denoise(z, bank, maps=[maps[0][:-1], maps[1]])
