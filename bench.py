@@ -24,6 +24,15 @@ GPU-trained banks, float16 host images in pinned memory, results copied back int
 staging buffers. It reports p50/p99 latency (arrival to device done, arrival to host done) and
 completed megapixels/s beside the offered load. Its latencies include both PCIe copies.
 
+The roofline object reports the dominant kernel, the batched form's level-0 filtering launch,
+against the HBM roofline (algorithmic bytes per launch / its HIP-event duration), with the unit that
+actually limits it (the LDS coefficient gathers) and the dot2 issue rate beside it.
+
+The CPU leg times the FP64 oracle on the leading crops of the batch and then reports the accuracy of
+the GPU results on that sample against it: bucket flips, max-abs at the GPU's maps, max-abs and
+|dPSNR| against pure FP64, and the training normal equations and coefficients of both Gram
+precisions against FP64 on two training pairs.
+
 Prints one JSON line. Run: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
 
@@ -56,21 +65,30 @@ ALU_PEAK_TFLOPS = 157.3
 FLOP_PER_PX = 2 * 3 * 98          # 3 channels x (49 upscale + 49 denoise) MACs per output pixel
 ALG_BYTES_F16 = 27.5625           # whole 4-level path, float16 storage and I/O, per level-0 pixel
 WALK_BYTES_PX_F16 = 13.5          # level-0 filter pass: read z (6) + coarser output (1.5) + write (6)
+# LDS bytes the filter pass gathers per pixel: 3 channels x 14 rows (7 upscale + 7 denoise) x 16 bytes
+WALK_LDS_BYTES_PX = 3 * 14 * 16
+# random 16-byte LDS gathers, measured at about 81 bytes per clock per CU: 256 CUs x 2.4 GHz
+LDS_GATHER_PEAK_GBS = 81 * 256 * 2.4
+
+
+ACC_CROPS, CROP = 8, 1024   # leading images, cropped, that the CPU baseline and the accuracy check run
 
 
 def _make_image(args):
-    seed, w, h, dt = args
-    z, _ = synth.noisy_pair(seed, h, w, 3, SIGMA, dtype=dt)
-    return z
+    seed, w, h, dt, keep_clean = args
+    z, u = synth.noisy_pair(seed, h, w, 3, SIGMA, dtype=dt)
+    return z, (np.ascontiguousarray(u[:, :CROP, :CROP]) if keep_clean else None)
 
 
 def make_inputs(n: int, dtype):
+    """The batch (noisy images) and the clean crops of its leading images, made in worker processes
+    before the GPU is touched."""
     sizes = synth.ragged_sizes(4, n)
-    jobs = [(4001 + i, w, h, dtype) for i, (w, h) in enumerate(sizes)]
+    jobs = [(4001 + i, w, h, dtype, i < ACC_CROPS) for i, (w, h) in enumerate(sizes)]
     workers = max(1, min(16, len(os.sched_getaffinity(0))))
     with mp.get_context("fork").Pool(workers) as pool:
-        imgs = pool.map(_make_image, jobs, chunksize=1)
-    return sizes, imgs
+        res = pool.map(_make_image, jobs, chunksize=1)
+    return sizes, [z for z, _ in res], [u for _, u in res if u is not None]
 
 
 def train_bank(M, torch, n_pairs=32, size=256, sigma=SIGMA):
@@ -157,12 +175,18 @@ def _make_serve_image(args):
     return z
 
 
-def run_served(M, torch, banks16, rates, n_requests):
-    """Open-loop Poisson traces through the serving loop; returns the per-rate report."""
+def make_serve_images():
+    """The served form's nine request images (size x sigma), made in worker processes before the GPU
+    is touched: a process forked after the HIP runtime started could inherit its held locks."""
     jobs = [(3 * si + gi, w, h, g) for si, (w, h) in enumerate(SERVE_SIZES) for gi, g in enumerate(SERVE_SIGMAS)]
     workers = max(1, min(9, len(os.sched_getaffinity(0))))
     with mp.get_context("fork").Pool(workers) as pool:
-        imgs = pool.map(_make_serve_image, jobs, chunksize=1)
+        return pool.map(_make_serve_image, jobs, chunksize=1)
+
+
+def run_served(M, torch, banks16, rates, n_requests, imgs):
+    """Open-loop Poisson traces through the serving loop; returns the per-rate report. Each request
+    size is also served alone once more and compared with the plain per-image form bit for bit."""
     host = [torch.from_numpy(z).pin_memory() for z in imgs]          # [size * 3 + sigma]
     staging = max(z.numel() for z in host) * 2
     srv = M.Server(banks16, storage=M.F16, max_slots=16, stages_per_tick=1, max_ticks_in_flight=2,
@@ -178,6 +202,14 @@ def run_served(M, torch, banks16, rates, n_requests):
             lat.append((c["t_host_done"] - c["t_arrival"]) * 1e3)
         alone[f"{w}x{h}"] = round(float(np.median(lat[1:])), 3)
     report = {"alone_host_ms": alone}
+    same = {}
+    for si, (w, h) in enumerate(SERVE_SIZES):
+        out_host = torch.empty_like(host[si * 3 + 1]).pin_memory()
+        srv.submit(host[si * 3 + 1], 1, out_host, tag=100 + si)
+        (c,) = srv.wait_all()
+        ref = M.denoise(host[si * 3 + 1].to("cuda:0"), banks16[1], M.F16).cpu()
+        same[f"{w}x{h}"] = bool(c["status"] == M.MDN_OK and torch.equal(out_host, ref))
+    report["bitwise_equal_to_plain"] = same
     # unmeasured warm-up at the highest rate: the first busy trace of a process pays one-time costs
     # (seen as a p99 of 11-17 ms against 6 ms for the same trace replayed afterwards)
     wrate = float(max(rates))
@@ -223,6 +255,7 @@ def run_served(M, torch, banks16, rates, n_requests):
 
 
 TRAIN_PAIRS, TRAIN_SIZE = 256, 512
+ACC_TRAIN_PAIRS = 2       # training pairs whose normal equations are checked against FP64
 FP32_MFMA_PEAK_TFLOPS = 157.3
 BF16_MFMA_PEAK_TFLOPS = 2500.0
 
@@ -233,20 +266,32 @@ def _make_train_pair(args):
     return z, u
 
 
-def run_training(M, torch, n_pairs=TRAIN_PAIRS, pool=True):
-    """Training throughput on 256 seeded 512x512 RGB pairs (sigma per pair from {15, 25, 50}/255,
-    rng(3)), 3-level pyramid: accumulation of the level-0 normal equations (D = 98 per channel, 67.1 M
-    samples) in both Gram precisions, then the level's FP64 solve (648 systems). The profiler probe
-    takes the first n_pairs of them, generated in this process (pool=False)."""
+def make_train_pairs(n_pairs=TRAIN_PAIRS, pool=True):
+    """256 seeded 512x512 RGB training pairs (sigma per pair from {15, 25, 50}/255, rng(3)); the
+    profiler probe takes the first n_pairs. Worker processes are forked before the GPU is touched."""
     rng = np.random.default_rng(3)
     sig = rng.choice([15.0, 25.0, 50.0], TRAIN_PAIRS)[:n_pairs]
     jobs = [(1 + i, float(g)) for i, g in enumerate(sig)]
     if pool:
         workers = max(1, min(16, len(os.sched_getaffinity(0))))
         with mp.get_context("fork").Pool(workers) as pool_:
-            pairs = pool_.map(_make_train_pair, jobs, chunksize=8)
-    else:
-        pairs = [_make_train_pair(j) for j in jobs]
+            return pool_.map(_make_train_pair, jobs, chunksize=8)
+    return [_make_train_pair(j) for j in jobs]
+
+
+def gram_mfma_flop(D, C, samples):
+    """FLOP the Gram kernel issues on the matrix cores: the feature vector plus the target (which
+    rides along as one more feature) is padded to T tiles of 32, and only the T(T+1)/2 tiles on and
+    above the diagonal are multiplied, 2 x 32 x 32 FLOP per tile and sample."""
+    T = -(-(D + 1) // 32)
+    return 2.0 * (T * (T + 1) // 2) * 32 * 32 * C * samples
+
+
+def run_training(M, torch, pairs):
+    """Training throughput, 3-level pyramid: accumulation of the level-0 normal equations (D = 98 per
+    channel; 67.1 M samples on the 256 pairs) in both Gram precisions, then the level's FP64 solve
+    (648 systems)."""
+    n_pairs = len(pairs)
     dev = torch.device("cuda:0")
     zs = [torch.from_numpy(z).to(dev) for z, _ in pairs]
     us = [torch.from_numpy(u).to(dev) for _, u in pairs]
@@ -258,7 +303,7 @@ def run_training(M, torch, n_pairs=TRAIN_PAIRS, pool=True):
     stream = torch.cuda.current_stream()
     samples = n_pairs * TRAIN_SIZE * TRAIN_SIZE
     useful = 2.0 * (D * D + D) * C * samples          # G and b products per sample and channel
-    issued = 2.0 * 128 * 128 * C * samples             # MFMA tiles cover D padded to 128
+    issued = gram_mfma_flop(D, C, samples)
     out = {"workload": f"{n_pairs} RGB pairs {TRAIN_SIZE}x{TRAIN_SIZE}, level 0 of a 3-level pyramid, "
                        f"D = 98 per channel, {K} buckets, {samples / 1e6:.1f} M samples"}
     g = None
@@ -288,7 +333,22 @@ def run_training(M, torch, n_pairs=TRAIN_PAIRS, pool=True):
     out["solve_ms"] = round(e0.elapsed_time(e1), 3)
     out["solve_systems"] = K * C
     out["fallback_systems"] = nfb
-    return out
+    # accuracy sample: the first ACC_TRAIN_PAIRS pairs accumulated in both precisions and solved; the
+    # CPU leg compares them with the FP64 normal equations over the same selector maps
+    sub = []
+    for z, u, c in list(zip(zs, us, coarse))[:ACC_TRAIN_PAIRS]:
+        sub.append({"z": z.cpu().numpy(), "u": u.cpu().numpy(), "coarse": c.cpu().numpy(),
+                    "s": M.select_filters(z, sel).cpu().numpy()})
+    res = {}
+    for name, prec in (("fp32_mfma", M.GRAM_F32), ("bf16x3_mfma", M.GRAM_BF16X3)):
+        g = M.Gram(K, C, RADIUS, RADIUS, device=dev)
+        for z, u, c in list(zip(zs, us, coarse))[:ACC_TRAIN_PAIRS]:
+            M.train_accumulate(g, z, u, sel, u_coarse=c, coarse_color=M.RGB, precision=prec)
+        co, nfb = M.train_solve(g, 1e-3)
+        res[name] = {"G": g.G.cpu().numpy().reshape(K, C, D, D), "n": g.n.cpu().numpy(),
+                     "h": co.double().cpu().numpy(), "fallback": nfb}
+    sample = {"pairs": sub, "results": res, "t_s": np.asarray(t_s), "t_c": np.asarray(t_c), "K": K, "C": C, "D": D}
+    return out, sample
 
 
 def time_level0_filter(M, torch, zs, bank, n=16, reps=3):
@@ -344,7 +404,7 @@ def pmc_probe():
     bench's batch of images through the batched form (autotuned strip heights), its launches once
     more one at a time: the last nine dispatches are the pyramid (levels 0 -> 1 -> 2 -> 3), then
     selection and filtering of levels 2, 1 and 0. The bank has random coefficients."""
-    sizes, imgs = make_inputs(N_IMAGES, np.float16)        # before the GPU is touched (worker pool)
+    sizes, imgs, _ = make_inputs(N_IMAGES, np.float16)     # before the GPU is touched (worker pool)
     import torch
     import paper_1802_06130_amd as M
     dev = torch.device("cuda:0")
@@ -367,24 +427,149 @@ def pmc_probe():
     print(f"pmc probe done: {len(zs)} images, {sum(w * h for w, h in sizes)} level-0 pixels", flush=True)
 
 
-def cpu_baseline(imgs, bank_dev, budget_s=20.0):
-    """The FP64 oracle on a bounded sample of the same workload (leading images, cropped)."""
-    import oracle as O
-    lvls = [O.LevelBank(lv.q_theta, lv.t_s, lv.t_c, lv.radius_g, None if lv.radius_f < 0 else lv.radius_f,
-                        lv.coeffs.double().cpu().numpy()) for lv in bank_dev.levels]
-    bank = O.Bank(lvls)
-    done_px, n, crop = 0, 0, 1024
+# The paper's own configuration (Section 5): 16 x 16 x 16 buckets at every level; 7x7 denoise and
+# 5x5 upscale filters (5x5 and 3x3 below sigma 10); as many pyramid levels as bring the coarsest
+# level's noise below 2 (noise sigma -> trained levels, radius_f, radius_g).
+PAPER_CONFIG = {5: (2, 1, 2), 15: (3, 2, 3), 25: (4, 2, 3), 50: (5, 2, 3)}
+
+
+def paper_frame_probe(sigma: int):
+    """The cascade of the paper's configuration at noise sigma on one seeded 4032x3024 float16 frame:
+    seeded stand-in float16 coefficients, thresholds at the equal-population quantiles of a
+    1024x1024 crop of the frame, 3 untimed and 5 timed mdn_denoise calls. For the profiler."""
+    if sigma not in PAPER_CONFIG:
+        raise SystemExit(f"--paper-frame: sigma one of {sorted(PAPER_CONFIG)}")
+    L, rf, rg = PAPER_CONFIG[sigma]
+    qt = qs = qc = 16
+    noisy = synth.noisy_pair(7, 3024, 4032, 3, float(sigma))[0]
+    import torch
+    import paper_1802_06130_amd as M
+    dev = torch.device("cuda:0")
+    frame = torch.from_numpy(noisy).to(dev).half()
+    t_s, t_c = M.level_thresholds([frame[:, :1024, :1024].float().contiguous()], qs, qc)
+    K = qt * qs * qc
+    levels = []
+    for lev in range(L):
+        co = synth.random_bank_coeffs(40 + lev, K, 3, (2 * rf + 1) ** 2, (2 * rg + 1) ** 2)
+        levels.append(M.Level(qt, t_s, t_c, rg, rf, torch.from_numpy(co).to(dev).half(), 3))
+    bank = M.Bank(levels)
+    out = torch.empty_like(frame)
+    ws = torch.empty(M.denoise_workspace_size(4032, 3024, 3, L, M.F16), dtype=torch.uint8, device=dev)
+    for _ in range(3):
+        M.denoise(frame, bank, storage=M.F16, ws=ws, out=out)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s * 0.6 and n < len(imgs):
-        z = imgs[n][:, :crop, :crop]
-        O.denoise(z, bank, storage=np.float16)
-        done_px += z.shape[1] * z.shape[2]
+    for _ in range(5):
+        M.denoise(frame, bank, storage=M.F16, ws=ws, out=out)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / 5 * 1e3
+    print(json.dumps({"sigma": sigma, "levels": L + 1, "buckets": K, "radius_f": rf, "radius_g": rg,
+                      "frame_ms_f16": round(ms, 3), "MP_s_f16": round(3024 * 4032 / ms * 1e-3, 1)}), flush=True)
+
+
+def accuracy_crops(imgs):
+    """The leading images of the batch cropped to at most CROP x CROP: the sample both the CPU
+    baseline and the accuracy check run."""
+    return [np.ascontiguousarray(z[:, :CROP, :CROP]) for z in imgs[:ACC_CROPS]]
+
+
+def gpu_crop_outputs(M, torch, crops, bank16):
+    """The crops through the headline (batched) form, and every level's selector map as the selection
+    walk writes it on the float16 pyramid."""
+    dev = torch.device("cuda:0")
+    zs = [torch.from_numpy(c).to(dev) for c in crops]
+    plan = M.Plan(bank16, M.F16, max_images=len(zs))
+    outs = plan.denoise_batch(zs, use_graph=True)
+    torch.cuda.synchronize()
+    plan.close()
+    res = []
+    for z, o in zip(zs, outs):
+        pyr = [z] + M.pyramid_build(z, LEVELS, storage=torch.float16)
+        maps = [M.select_filters(pyr[lev], bank16.levels[lev]).cpu().numpy().astype(np.int64)
+                for lev in range(LEVELS)]
+        res.append((o.float().cpu().numpy().astype(np.float64), maps))
+    return res
+
+
+def cpu_baseline_leg(crops, clean_crops, gpu_crops, bank16_dev, bank32_dev, train_sample, budget_s=20.0):
+    """The FP64 oracle on a bounded sample of the same workload (the leading crops), timed; then the
+    accuracy of the GPU results on that sample against it:
+    * inference (the crops through the batched form): bucket flips per level against the oracle's
+      selection on the same float16 pyramid, all of them near a boundary (oracle margin < 1e-6);
+      max-abs over every pixel against the oracle's float16-storage mode run on the GPU's maps with
+      the same float16 coefficients; and max-abs and |dPSNR| against the pure FP64 oracle with the
+      bank as trained (float32 coefficients, no storage rounding);
+    * training (ACC_TRAIN_PAIRS pairs of the training workload): the worst Gram entry error relative
+      to sqrt(G_pp G_qq), the coefficient max-abs and the output-space error
+      sqrt(sum dh^T G dh / sum y^2) of both Gram precisions against the FP64 normal equations
+      accumulated over the same selector maps and solved in FP64."""
+    import oracle as O
+
+    def host_bank(b):
+        return O.Bank([O.LevelBank(lv.q_theta, lv.t_s, lv.t_c, lv.radius_g, None if lv.radius_f < 0 else lv.radius_f,
+                                   lv.coeffs.double().cpu().numpy()) for lv in b.levels])
+    bank, bank64 = host_bank(bank16_dev), host_bank(bank32_dev)
+    done_px, n = 0, 0
+    own = []
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s * 0.6 and n < len(crops):
+        own.append(O.denoise(crops[n], bank, storage=np.float16, return_index_maps=True))
+        done_px += crops[n].shape[1] * crops[n].shape[2]
         n += 1
     dt = time.perf_counter() - t0
-    return {"value": round(done_px / dt / 1e6, 4), "unit": "MP/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} leading image(s) of the batch cropped to at most {crop}x{crop} "
+    base = {"value": round(done_px / dt / 1e6, 4), "unit": "MP/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} leading image(s) of the batch cropped to at most {CROP}x{CROP} "
                       f"({done_px / 1e6:.2f} MP), 4-level FP64 NumPy oracle in float16-storage mode, "
                       f"one process (host affinity {len(os.sched_getaffinity(0))} cpus)"}
+    acc = {"inference": {"crops": n, "form": "batched (plan, hipGraph), float16 storage and filters",
+                         "flips_per_level": [0] * LEVELS, "near_boundary_per_level": [0] * LEVELS,
+                         "flips_away_from_boundary": 0,
+                         "max_abs_vs_fp16_mode_at_gpu_maps": 0.0, "max_abs_vs_fp64": 0.0, "dpsnr_vs_fp64_db": 0.0}}
+    inf = acc["inference"]
+    for i in range(n):
+        ref16, omaps = own[i]
+        got, gmaps = gpu_crops[i]
+        pyr = O.build_pyramid(crops[i], LEVELS + 1, storage=np.float16)
+        flipped = False
+        for lev in range(LEVELS):
+            lb = bank.levels[lev]
+            _, margin = O.select(np.asarray(pyr[lev], np.float64), lb.q_theta, lb.t_s, lb.t_c, return_margin=True)
+            mism = gmaps[lev] != omaps[lev]
+            near = margin < 1e-6
+            inf["flips_per_level"][lev] += int(mism.sum())
+            inf["near_boundary_per_level"][lev] += int(near.sum())
+            inf["flips_away_from_boundary"] += int((mism & ~near).sum())
+            flipped |= bool(mism.any())
+        at = O.denoise(crops[i], bank, storage=np.float16, maps=gmaps) if flipped else ref16
+        ref64 = O.denoise(np.asarray(crops[i], np.float64), bank64)
+        clean = np.asarray(clean_crops[i], np.float64)
+        inf["max_abs_vs_fp16_mode_at_gpu_maps"] = max(inf["max_abs_vs_fp16_mode_at_gpu_maps"],
+                                                     float(np.max(np.abs(got - at))))
+        inf["max_abs_vs_fp64"] = max(inf["max_abs_vs_fp64"], float(np.max(np.abs(got - ref64))))
+        inf["dpsnr_vs_fp64_db"] = max(inf["dpsnr_vs_fp64_db"], abs(O.psnr(got, clean) - O.psnr(ref64, clean)))
+    for k in ("max_abs_vs_fp16_mode_at_gpu_maps", "max_abs_vs_fp64"):
+        inf[k] = float(f"{inf[k]:.3g}")
+    inf["dpsnr_vs_fp64_db"] = round(float(inf["dpsnr_vs_fp64_db"]), 5)
+    if train_sample is not None:
+        ts = train_sample
+        K, C, D = ts["K"], ts["C"], ts["D"]
+        st = O.GramStats.zeros(K, C, D)
+        for p in ts["pairs"]:
+            O.accumulate_level(st, p["s"].astype(np.int64), O.to_filter_space(np.asarray(p["z"], np.float64)),
+                               O.to_filter_space(np.asarray(p["u"], np.float64)), RADIUS, RADIUS,
+                               O.to_filter_space(np.asarray(p["coarse"], np.float64)))
+        href, _ = O.solve_level(st, 1e-3)
+        d = np.sqrt(np.maximum(np.einsum("kcii->kci", st.G), 0.0))
+        tr = {"pairs": len(ts["pairs"]), "samples": int(st.n.sum()), "lambda": 1e-3}
+        for name, r in ts["results"].items():
+            dh = r["h"] - href
+            e = np.einsum("kcd,kcde,kce->", dh, st.G, dh)
+            tr[name] = {"counts_equal": bool(np.array_equal(r["n"], st.n)),
+                        "gram_worst_rel": float(f"{np.max(np.abs(r['G'] - st.G) / (d[..., :, None] * d[..., None, :] + 1e-300)):.3g}"),
+                        "coeff_max_abs": float(f"{np.max(np.abs(dh)):.3g}"),
+                        "output_space_rel": float(f"{np.sqrt(max(e, 0.0) / st.yy.sum()):.3g}")}
+        acc["training"] = tr
+    return base, acc
 
 
 def main():
@@ -398,6 +583,8 @@ def main():
     ap.add_argument("--pmc-probe", action="store_true", help="run only the hardware-counter probe")
     ap.add_argument("--train-probe", action="store_true",
                     help="run only the training measurement on 64 pairs, without worker processes (for the profiler)")
+    ap.add_argument("--paper-frame", type=int, default=None, metavar="SIGMA",
+                    help="run only the paper-configuration frame probe at this noise level (for the profiler)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-train", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2000)
@@ -405,23 +592,30 @@ def main():
     if args.pmc_probe:
         pmc_probe()
         return
+    if args.paper_frame is not None:
+        paper_frame_probe(args.paper_frame)
+        return
     if args.train_probe:
+        pairs = make_train_pairs(64, pool=False)
         import torch
         import paper_1802_06130_amd as M
-        print(json.dumps(run_training(M, torch, n_pairs=64, pool=False)), flush=True)
+        print(json.dumps(run_training(M, torch, pairs)[0]), flush=True)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU; the library has no multi-GPU path (images are independent "
               "and would be routed to GPUs one by one).", file=sys.stderr)
         sys.exit(2)
 
+    # every worker pool runs before the GPU is touched
+    t_gen = time.perf_counter()
+    sizes, imgs, clean_crops = make_inputs(args.images, np.float16)
+    train_pairs = None if args.no_train else make_train_pairs()
+    serve_imgs = None if args.no_serve else make_serve_images()
+    print(f"# generated {len(imgs)} images ({sum(w * h for w, h in sizes) / 1e6:.1f} MP) and the training and "
+          f"serving inputs in {time.perf_counter() - t_gen:.1f}s", file=sys.stderr, flush=True)
+
     import torch
     import paper_1802_06130_amd as M
-
-    t_gen = time.perf_counter()
-    sizes, imgs = make_inputs(args.images, np.float16)
-    print(f"# generated {len(imgs)} images ({sum(w * h for w, h in sizes) / 1e6:.1f} MP) "
-          f"in {time.perf_counter() - t_gen:.1f}s", file=sys.stderr, flush=True)
     dev = torch.device("cuda:0")
     t_tr = time.perf_counter()
     bank32, fbs = train_bank(M, torch)
@@ -455,6 +649,7 @@ def main():
     img_px, img_dur = time_level0_filter(M, torch, zs, bank16)
     flops = FLOP_PER_PX * avg_px / avg_dur / 1e12
     hbm = WALK_BYTES_PX_F16 * avg_px / avg_dur / 1e9
+    lds = WALK_LDS_BYTES_PX * avg_px / avg_dur / 1e9
     tr = measured_traffic()
     line = {
         "metric": "megapixels/s denoised (4-level RGB 7x7) + p99 latency; batched vs plain per-image",
@@ -487,24 +682,42 @@ def main():
                             "step_ms_events": round(float(np.median(ms_steps)), 3)},
         "whole_path_hbm": {"algorithmic_bytes_per_px": ALG_BYTES_F16,
                            "frac": round(value * 1e6 * ALG_BYTES_F16 / (HBM_PEAK_GBS * 1e9), 4)},
-        "roofline": {"bound": "alu", "achieved": round(flops, 2), "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(flops / ALU_PEAK_TFLOPS, 4),
+        "roofline": {"bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(hbm / HBM_PEAK_GBS, 4),
                      "traffic": None if tr is None else round(tr["hbm_bytes_per_px"] * avg_px),
-                     "kernel": "k_walk, level-0 filtering launch of the batched form (all images of the step; "
-                               "3 x 98 float16 dot2 MACs per pixel)",
-                     "algorithmic_flop_per_launch": round(FLOP_PER_PX * avg_px),
-                     "avg_launch_us": round(avg_dur * 1e6, 2),
-                     "hbm_achieved_GBs": round(hbm, 1), "hbm_frac": round(hbm / HBM_PEAK_GBS, 4),
+                     "traffic_source": None if tr is None else
+                     ("profiles/walk_level0_traffic.json: rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE of this launch, "
+                      "scaled by a copy kernel of known size, taken at the current walk.hip (sha256 "
+                      f"{tr['walk_hip_sha256_16']}); carried from that file, not measured in this run"),
+                     "kernel": "k_walk, level-0 filtering launch of the batched form (all images of the step)",
                      "algorithmic_bytes_per_launch": round(WALK_BYTES_PX_F16 * avg_px),
+                     "algorithmic_bytes_per_px": WALK_BYTES_PX_F16,
+                     "avg_launch_us": round(avg_dur * 1e6, 2),
+                     "limiter": {
+                         "unit": "lds",
+                         "what": "the kernel is bound by its LDS coefficient gathers, not by HBM: the same launch "
+                                 "against each unit's ceiling",
+                         "lds_gather_GBs": round(lds, 1), "lds_gather_bytes_per_px": WALK_LDS_BYTES_PX,
+                         "lds_random_gather_ceiling_GBs": LDS_GATHER_PEAK_GBS,
+                         "lds_frac": round(lds / LDS_GATHER_PEAK_GBS, 4),
+                         "dot2_TFLOPs": round(flops, 2), "dot2_peak_TFLOPs": ALU_PEAK_TFLOPS,
+                         "dot2_frac": round(flops / ALU_PEAK_TFLOPS, 4),
+                         "algorithmic_flop_per_px": FLOP_PER_PX,
+                         "hbm_frac": round(hbm / HBM_PEAK_GBS, 4)},
                      "kernel_us_per_level": [[round(t, 1) for t in lv] for lv in ktimes],
+                     "kernel_us_order": "per level 0, 1, 2: pyramid (level l -> l+1), selection, filtering",
                      "per_image_launch": {"mean_px": round(img_px), "avg_launch_us": round(img_dur * 1e6, 2),
                                           "TFLOP/s": round(FLOP_PER_PX * img_px / img_dur / 1e12, 2),
                                           "what": "the same kernel launched per image on the first 16 images"}},
     }
     if f32 is not None:
         line["plain_f32"] = f32
+    crops = accuracy_crops(imgs)
+    gpu_crops = gpu_crop_outputs(M, torch, crops, bank16) if not args.no_cpu_baseline else None
+    train_sample = None
     if not args.no_train:
-        line["training"] = run_training(M, torch)
+        line["training"], train_sample = run_training(M, torch, train_pairs)
+        del train_pairs
     if not args.no_serve:
         del zs
         torch.cuda.empty_cache()
@@ -512,9 +725,10 @@ def main():
         for g in SERVE_SIGMAS:
             b32 = bank32 if g == SIGMA else train_bank(M, torch, sigma=g)[0]
             banks.append(as_dtype(M, b32, torch.float16))
-        line["served"] = run_served(M, torch, banks, (50, 200, 800), args.serve_requests)
+        line["served"] = run_served(M, torch, banks, (50, 200, 800), args.serve_requests, serve_imgs)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(imgs, bank32)
+        line["cpu_baseline"], line["accuracy"] = cpu_baseline_leg(crops, clean_crops, gpu_crops, bank16, bank32,
+                                                                  train_sample)
     print(json.dumps(line), flush=True)
 
 

@@ -79,13 +79,15 @@ std::vector<uint64_t> signature(const mdn_image* in, const mdn_image* out, int n
     s.reserve(n * 8 + 1);
     s.push_back((uint64_t)n);
     for (int i = 0; i < n; ++i) {
+        // every field that the tables or the captured launches depend on, each in a word of its own
         s.push_back((uint64_t)in[i].data);
         s.push_back((uint64_t)out[i].data);
-        s.push_back(((uint64_t)in[i].width << 32) | (uint32_t)in[i].height);
+        s.push_back(((uint64_t)(uint32_t)in[i].width << 32) | (uint32_t)in[i].height);
         s.push_back((uint64_t)in[i].row_pitch);
         s.push_back((uint64_t)in[i].plane_pitch);
-        s.push_back((uint64_t)out[i].row_pitch ^ ((uint64_t)out[i].plane_pitch << 20));
-        s.push_back(((uint64_t)in[i].dtype << 8) | (uint64_t)out[i].dtype);
+        s.push_back((uint64_t)out[i].row_pitch);
+        s.push_back((uint64_t)out[i].plane_pitch);
+        s.push_back(((uint64_t)(uint32_t)in[i].dtype << 8) | (uint32_t)out[i].dtype);
     }
     return s;
 }

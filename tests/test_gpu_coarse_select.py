@@ -15,7 +15,7 @@ import pytest
 
 import oracle as O
 import synth
-from mdn_testlib import (TOL_F16, TOL_F32, check_gram, gpu_bank, gpu_level, index_parity, max_abs,
+from mdn_testlib import (FLIP_CAP, TOL_F16, TOL_F32, check_gram, gpu_bank, gpu_level, index_parity, max_abs,
                          trained_bank_multiscale)
 
 pytestmark = pytest.mark.gpu
@@ -132,20 +132,14 @@ def _gpu_levels(img, gb, storage_t, coeff16):
 
 def _oracle_on_maps(img, bank, maps, storage):
     """The oracle cascade with the GPU's index maps."""
-    L = len(bank.levels)
-    pyr = O.build_pyramid(img, L + 1, storage)
-    u = O.to_filter_space(pyr[L])
-    for lev in range(L - 1, -1, -1):
-        u = O.apply_level(O.to_filter_space(pyr[lev]), maps[lev], bank.levels[lev], u_coarse=u)
-        if lev > 0:
-            u = O.round_storage(u, storage)
-    return O.round_storage(O.from_filter_space(u), storage)
+    return O.denoise(img, bank, storage=storage, maps=maps)
 
 
 def _check_maps(maps, coarse, pyr_host, bank):
     for lev, (uc, ycc) in enumerate(coarse):
         _, n_mis, n_near = index_parity(maps[lev], pyr_host[lev], bank.levels[lev], u_coarse=_filter_space(uc, ycc))
         print(f"  level {lev}: mismatches={n_mis} near-boundary={n_near}")
+        assert n_mis <= max(1, FLIP_CAP * maps[lev].size)
 
 
 @pytest.mark.parametrize("H,W", [(9, 13), (200, 328)])

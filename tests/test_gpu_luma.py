@@ -13,7 +13,7 @@ import pytest
 
 import oracle as O
 import synth
-from mdn_testlib import (TOL_F16, TOL_F32, gpu_bank, gpu_level, index_parity, max_abs, propagate_mask,
+from mdn_testlib import (TOL_F16, TOL_F32, cascade_parity, gpu_bank, gpu_level, index_parity,
                          trained_bank_multiscale)
 
 pytestmark = pytest.mark.gpu
@@ -89,36 +89,14 @@ def test_luma_misses_the_equal_luma_edge_on_the_gpu():
     assert s[16, 32] // 3 % 3 == 2
 
 
-def _cascade(img, bank, storage, storage_t, tol):
-    import paper_1802_06130_amd as M
-    C, L = img.shape[0], len(bank.levels)
-    gb = gpu_bank(bank, C)
-    out = _host(M.denoise(_dev(img), gb, storage=M.F32 if storage == np.float32 else M.F16))
-    ref = O.denoise(img, bank, storage=storage)
-    pyr_g = M.pyramid_build(_dev(img), L, storage=storage_t)
-    pyr_o = O.build_pyramid(img, L + 1, storage=storage)
-    mask = np.zeros(pyr_o[L - 1].shape[1:], bool)
-    for lev in range(L - 1, -1, -1):
-        zg = _dev(img) if lev == 0 else pyr_g[lev - 1]
-        s = M.select_filters(zg, gb.levels[lev]).cpu().numpy()
-        mism, _, _ = index_parity(s, pyr_o[lev], bank.levels[lev])
-        if lev < L - 1:
-            mask = propagate_mask(mask, mism.shape, bank.levels[lev].radius_f)
-        mask = mask | mism
-    err = max_abs(out, ref, mask)
-    print(f"  max-abs={err:.3g} excluded px={int(mask.sum())}")
-    assert err <= tol
-    return out
-
-
 @pytest.mark.parametrize("H,W", [(9, 13), (200, 328)])
 def test_denoise_luma_bank_f32(H, W):
     print(f"denoise luma 3-level f32 {H}x{W}", flush=True)
     bank = trained_bank_multiscale(levels=2, selector="luma")
     z, u = synth.noisy_pair(2003, H, W, 3, 25)
-    out = _cascade(z, bank, np.float32, _torch().float32, TOL_F32)
+    r = cascade_parity(z, bank, gpu_bank(bank, 3), np.float32, TOL_F32, u=u)
     if H * W > 10000:
-        assert O.psnr(out, u) > O.psnr(z, u) + 5
+        assert O.psnr(r["out"], u) > O.psnr(z, u) + 5
 
 
 def test_denoise_luma_bank_f16_column_walk():
@@ -129,22 +107,7 @@ def test_denoise_luma_bank_f16_column_walk():
     bank = trained_bank_multiscale(levels=3, selector="luma")
     z, u = synth.noisy_pair(4009, 250, 330, 3, 25, dtype=np.float16)
     gb = gpu_bank(bank, 3, coeff_dtype=torch.float16)
-    out = _host(M.denoise(_dev(z), gb, storage=M.F16))
-    ref16 = O.denoise(z, bank, storage=np.float16)
-    L = 3
-    pyr_g = M.pyramid_build(_dev(z), L, storage=torch.float16)
-    pyr_o = O.build_pyramid(z, L + 1, storage=np.float16)
-    mask = np.zeros(pyr_o[L - 1].shape[1:], bool)
-    for lev in range(L - 1, -1, -1):
-        zg = _dev(z) if lev == 0 else pyr_g[lev - 1]
-        s = M.select_filters(zg, gb.levels[lev]).cpu().numpy()
-        mism, _, _ = index_parity(s, pyr_o[lev], bank.levels[lev])
-        if lev < L - 1:
-            mask = propagate_mask(mask, mism.shape, bank.levels[lev].radius_f)
-        mask = mask | mism
-    err = max_abs(out, ref16, mask)
-    print(f"  max-abs vs fp16-mode oracle {err:.3g}")
-    assert err <= TOL_F16
+    cascade_parity(z, bank, gb, np.float16, TOL_F16, u=u)
     # batched form over ragged images: bit-identical to the per-image form
     zs = [_dev(synth.noisy_pair(4100 + i, h, w, 3, 25, dtype=np.float16)[0]) for i, (h, w) in
           enumerate([(250, 330), (61, 97), (128, 40)])]

@@ -12,7 +12,7 @@ import pytest
 
 import oracle as O
 import synth
-from mdn_testlib import TOL_F32, gpu_bank, gpu_level, index_parity, max_abs, propagate_mask
+from mdn_testlib import TOL_F32, cascade_parity, gpu_bank, gpu_level, index_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -70,22 +70,7 @@ def test_denoise_phase_aware_f32():
     bank = _bank(2)
     z, u = synth.noisy_pair(2020, 200, 248, 3, 25)
     gb = gpu_bank(bank, 3)
-    out = _host(M.denoise(_dev(z), gb, storage=M.F32))
-    ref = O.denoise(z, bank, storage=np.float32)
-    L = 2
-    pyr_g = M.pyramid_build(_dev(z), L, storage=torch.float32)
-    pyr_o = O.build_pyramid(z, L + 1, storage=np.float32)
-    mask = np.zeros(pyr_o[L - 1].shape[1:], bool)
-    for lev in range(L - 1, -1, -1):
-        zg = _dev(z) if lev == 0 else pyr_g[lev - 1]
-        s = M.select_filters(zg, gb.levels[lev]).cpu().numpy()
-        mism, _, _ = index_parity(s, pyr_o[lev], bank.levels[lev])
-        if lev < L - 1:
-            mask = propagate_mask(mask, mism.shape, 3)
-        mask = mask | mism
-    err = max_abs(out, ref, mask)
-    print(f"  max-abs={err:.3g} excluded px={int(mask.sum())}")
-    assert err <= TOL_F32
+    cascade_parity(z, bank, gb, np.float32, TOL_F32, u=u)
 
 
 def test_train_phase_aware_end_to_end():
