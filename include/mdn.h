@@ -171,6 +171,20 @@ mdn_status mdn_denoise_workspace_size(int32_t width, int32_t height, int32_t cha
 mdn_status mdn_denoise(const mdn_image* in, const mdn_bank* bank, int32_t storage, void* ws,
                        size_t ws_bytes, const mdn_image* out, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): mdn_denoise with its workspace taken from a static
+ * device array of MDN_NOALLOC_SCRATCH_BYTES, which the library holds on every device it runs on
+ * until the process ends. The call allocates nothing; the caller still owns `in` and `out`.
+ * Arguments, results and errors are those of mdn_denoise, plus MDN_ENOMEM when the image needs
+ * more workspace than the array holds (mdn_denoise_workspace_size; a 4032 x 3024 RGB frame fits
+ * at either storage) and MDN_EDEVICE when the array's address cannot be obtained. The current
+ * device must be the one `stream` belongs to. Every call on one device uses the same array:
+ * calls that overlap in time on one device (several streams, several host threads) race and
+ * must be serialised by the caller; calls in order on one stream are safe. */
+#define MDN_NOALLOC_SCRATCH_BYTES (128ull << 20)
+mdn_status mdn_denoise_noalloc(const mdn_image* in, const mdn_bank* bank, int32_t storage,
+                               const mdn_image* out, void* stream);
+
 /* ---------------------------------------------------------------------------------------
  * Training (Eq. (7)-(8)): one least-squares regression per bucket (and per YCbCr channel,
  * footnote of Section 3), level by level from the second-coarsest level down (Section 4).

@@ -4,7 +4,7 @@
 from ._lib import (  # noqa: F401
     F16, F32, GRAY, RGB, YCC, SELECT_COARSE, SELECT_LUMA, SELECT_RGB,
     Bank, Level, MdnError,
-    apply_level, denoise, denoise_workspace_size, header_functions, image, lib,
+    apply_level, denoise, denoise_noalloc, denoise_workspace_size, NOALLOC_SCRATCH_BYTES, header_functions, image, lib,
     pyramid_build, select_filters, selector_dtype, dihedral, augment_pairs,
     GRAM_BF16X3, GRAM_F32, X_CROSS_CHANNEL, X_PER_CHANNEL, Gram, level_features, level_thresholds,
     quantiles, train_accumulate, train_multiscale, train_single, train_solve, Plan,

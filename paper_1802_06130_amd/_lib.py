@@ -70,6 +70,7 @@ def lib() -> ct.CDLL:
             "mdn_apply_level": [P(MdnImage), P(MdnImage), vp, i64, P(MdnLevel), P(MdnImage), vp, vp],
             "mdn_denoise_workspace_size": [i32, i32, i32, i32, i32, P(ct.c_size_t)],
             "mdn_denoise": [P(MdnImage), P(MdnBank), i32, vp, ct.c_size_t, P(MdnImage), vp],
+            "mdn_denoise_noalloc": [P(MdnImage), P(MdnBank), i32, P(MdnImage), vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -274,6 +275,21 @@ def denoise(img, bank: Bank, storage: int = F32, ws=None, out=None):
     b = bank.desc()
     _check(lib().mdn_denoise(ct.byref(image(img)), ct.byref(b), storage, ct.c_void_p(ws.data_ptr()),
                              ws.numel(), ct.byref(image(out)), _stream_ptr()))
+    return out
+
+
+NOALLOC_SCRATCH_BYTES = 128 << 20     # MDN_NOALLOC_SCRATCH_BYTES of include/mdn.h
+
+
+def denoise_noalloc(img, bank: Bank, storage: int = F32, out=None):
+    """mdn_denoise_noalloc: the cascade with the library's static device scratch as workspace (the
+    library allocates nothing; ``out`` is allocated here unless given). Calls that overlap on one
+    device race on that scratch."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty_like(img)
+    b = bank.desc()
+    _check(lib().mdn_denoise_noalloc(ct.byref(image(img)), ct.byref(b), storage, ct.byref(image(out)), _stream_ptr()))
     return out
 
 

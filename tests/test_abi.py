@@ -111,6 +111,27 @@ def test_denoise_workspace_too_small():
     assert st == B.MDN_ENOMEM
 
 
+def test_noalloc_refuses_an_image_above_its_scratch_before_touching_the_device():
+    """The entry point that allocates nothing checks the cascade's workspace against its static scratch
+    (MDN_NOALLOC_SCRATCH_BYTES) first: a 16384 x 8192 float32 image needs more and is refused."""
+    w, h = 16384, 8192
+    z = B.MdnImage(0x1000, w, h, 3, M.F32, M.RGB, 0, w, w * h)
+    out = B.MdnImage(0x2000, w, h, 3, M.F32, M.RGB, 0, w, w * h)
+    lv = (B.MdnLevel * 3)(_level(), _level(), _level())
+    bank = B.MdnBank(3, 0, ct.cast(lv, ct.POINTER(B.MdnLevel)))
+    assert M.denoise_workspace_size(w, h, 3, 3, M.F32) > M.NOALLOC_SCRATCH_BYTES
+    st = M.lib().mdn_denoise_noalloc(ct.byref(z), ct.byref(bank), M.F32, ct.byref(out), None)
+    assert st == B.MDN_ENOMEM and b"static scratch" in M.lib().mdn_last_error()
+    assert M.denoise_workspace_size(4032, 3024, 3, 4, M.F32) <= M.NOALLOC_SCRATCH_BYTES
+
+
+def test_noalloc_scratch_size_matches_the_header():
+    import re
+    with open(B.HEADER_PATH) as fh:
+        m = re.search(r"#define MDN_NOALLOC_SCRATCH_BYTES \((\d+)ull << (\d+)\)", fh.read())
+    assert m and int(m.group(1)) << int(m.group(2)) == M.NOALLOC_SCRATCH_BYTES
+
+
 def test_library_missing_fails_loudly(tmp_path, monkeypatch):
     monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "nope.so"))
     monkeypatch.setattr(B, "_lib", None)
