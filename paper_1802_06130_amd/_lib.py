@@ -15,7 +15,8 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libmdn.so")
+# MDN_LIB names another build of the same library (the sanitizer variants of build.py)
+LIB_PATH = os.environ.get("MDN_LIB") or os.path.join(_PKG, "libmdn.so")
 HEADER_PATH = os.path.join(os.path.dirname(_PKG), "include", "mdn.h")
 
 MDN_OK, MDN_EINVAL, MDN_ENOMEM, MDN_EDEVICE, MDN_ENOTSUP, MDN_ETIMEOUT, MDN_ECANCELED = range(7)
