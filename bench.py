@@ -28,6 +28,9 @@ The roofline object reports the dominant kernel, the batched form's level-0 filt
 against the HBM roofline (algorithmic bytes per launch / its HIP-event duration), with the unit that
 actually limits it (the LDS coefficient gathers) and the dot2 issue rate beside it.
 
+The paper's own configuration at sigma 25 (16 x 16 x 16 buckets, 7x7 / 5x5 filters, 5 levels,
+float16) runs the same batch in the batched form beside it (paper_config_batched).
+
 The CPU leg times the FP64 oracle on the leading crops of the batch and then reports the accuracy of
 the GPU results on that sample against it: bucket flips, max-abs at the GPU's maps, max-abs and
 |dPSNR| against pure FP64, and the training normal equations and coefficients of both Gram
@@ -351,6 +354,42 @@ def run_training(M, torch, pairs):
     return out, sample
 
 
+def run_paper_config_batched(M, torch, zs, steps, warmup, sigma=25):
+    """The paper's own configuration (Section 5) at sigma 25 on the same batch: 16 x 16 x 16 buckets,
+    7x7 denoise and 5x5 upscale filters, 5 pyramid levels, trained on the GPU from the bench's 32
+    training pairs (most of the 4096 buckets take the pooled solution with this little data), float16
+    coefficients and storage; batched form (one tiled launch per level, selection inline, hipGraph
+    replay). Returns its rate and whether it equals the per-image form on the first images."""
+    L, rf, rg = PAPER_CONFIG[sigma]
+    pairs = [synth.noisy_pair(7000 + i, 256, 256, 3, float(sigma)) for i in range(32)]
+    dev = torch.device("cuda:0")
+    pairs = [(torch.from_numpy(z).to(dev), torch.from_numpy(u).to(dev)) for z, u in pairs]
+    b32, _, fbs = M.train_multiscale(pairs, L, 16, 16, 16, rf, rg, 1e-3)
+    bank = M.Bank([M.Level(lv.q_theta, lv.t_s, lv.t_c, lv.radius_g, lv.radius_f, lv.coeffs.half(), 3)
+                   for lv in b32.levels])
+    plan = M.Plan(bank, M.F16, max_images=len(zs))
+    outs = [torch.empty_like(z) for z in zs]
+    plan.autotune(zs, outs)
+    for _ in range(warmup):
+        plan.denoise_batch(zs, outs, use_graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.denoise_batch(zs, outs, use_graph=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = plan.kernel_times(zs, outs, reps=1)
+    plan.close()
+    same = all(torch.equal(outs[i], M.denoise(zs[i], bank, storage=M.F16)) for i in range(4))
+    px = sum(z.shape[1] * z.shape[2] for z in zs)
+    return {"value": round(px * steps / wall / 1e6, 2), "unit": "MP/s", "ms_per_step": round(wall * 1e3 / steps, 3),
+            "steps": steps, "levels": L + 1, "buckets": 4096, "radius_f": rf, "radius_g": rg,
+            "fallback_systems": fbs, "bitwise_equal_to_plain_first4": bool(same),
+            "kernel_us_per_level": [[round(t, 1) for t in lv] for lv in kt],
+            "what": "paper configuration at sigma 25 (16x16x16 buckets, 7x7 g / 5x5 f, 5 levels), float16, "
+                    "batched form on the same 64 images: tiled select-and-filter kernel, one launch per level"}
+
+
 def time_level0_filter(M, torch, zs, bank, n=16, reps=3):
     """The dominant kernel, the level-0 filtering pass, timed alone with HIP events on its stream
     (the selector map and the coarser output are prepared first)."""
@@ -586,6 +625,7 @@ def main():
     ap.add_argument("--paper-frame", type=int, default=None, metavar="SIGMA",
                     help="run only the paper-configuration frame probe at this noise level (for the profiler)")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-paper-config", action="store_true")
     ap.add_argument("--no-train", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2000)
     args = ap.parse_args()
@@ -712,6 +752,9 @@ def main():
     }
     if f32 is not None:
         line["plain_f32"] = f32
+    if not args.no_paper_config:
+        line["paper_config_batched"] = run_paper_config_batched(M, torch, zs, max(2, args.steps // 2), 1)
+        print(f"# paper configuration batched: {line['paper_config_batched']}", file=sys.stderr, flush=True)
     crops = accuracy_crops(imgs)
     gpu_crops = gpu_crop_outputs(M, torch, crops, bank16) if not args.no_cpu_baseline else None
     train_sample = None

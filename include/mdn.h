@@ -276,8 +276,16 @@ mdn_status mdn_quantiles(const double* values, int64_t n, int32_t q, double* out
  * --------------------------------------------------------------------------------------- */
 typedef struct mdn_plan mdn_plan;
 
-/* Create a plan for a float16 7x7/7x7 colour bank (K <= 243 per level, every level selecting on
- * its own input: coarse-selector levels return MDN_ENOTSUP, as do phase-aware ones). The plan copies the
+/* Create a plan for a multiscale colour bank. Each level runs in the batched form on the kernel
+ * mdn_denoise uses for it, so batched outputs equal per-image ones bit for bit:
+ *  - float16 7x7/7x7 levels of up to 243 buckets: a selection pass and the filtering column walk
+ *    (strip heights autotuned);
+ *  - levels that mdn_denoise filters with the tiled select-and-filter kernel (among them the
+ *    paper's own configuration of Section 5: 16 x 16 x 16 buckets with 7x7 / 5x5 or 5x5 / 3x3
+ *    filters, phase-aware banks, float16 or float32 coefficients): one launch per level over the
+ *    64 x 16 tiles of every image, selection inline, coefficients read through the caches.
+ * MDN_ENOTSUP for single-scale banks, float32 banks that fit in LDS one channel at a time, and
+ * float16 7x7/7x7 levels that select on the coarser output. The plan copies the
  * level descriptors and thresholds (the coefficient buffers must stay valid while it is used),
  * creates its own stream, and allocates its device workspace and tables on first use: creation
  * and the first batch of a new size are the only calls that allocate. storage: pyramid dtype. */
@@ -293,7 +301,8 @@ mdn_status mdn_plan_autotune(mdn_plan* plan, const mdn_image* in, const mdn_imag
 /* Device time of every launch of this batch: the launches of mdn_denoise_batch, in the same order
  * and with the same strip heights but without a graph, each started on the idle plan stream between
  * two HIP events, `reps` times (1..1000); us_out (host float[3*levels]) receives the mean microseconds per
- * launch of the pyramid, selection and filtering kernels of each level (index 3 l + k). The outputs
+ * launch of the pyramid, selection and filtering kernels of each level (index 3 l + k; a level on the
+ * tiled kernel reports its one launch as filtering and about nothing for selection). The outputs
  * are written as by mdn_denoise_batch. Synchronises the plan's stream. */
 mdn_status mdn_plan_kernel_times(mdn_plan* plan, const mdn_image* in, const mdn_image* out, int32_t n,
                                  int32_t reps, float* us_out, void* stream);
@@ -326,7 +335,10 @@ typedef struct mdn_server mdn_server;
 typedef enum { MDN_EXEC_HIP = 0, MDN_EXEC_FAKE = 1 } mdn_executor_kind;
 
 typedef struct mdn_server_config {
-    const mdn_bank* banks;        /* n_banks float16 7x7/7x7 colour banks (K <= 243 per level, each level selecting on its own input); the
+    const mdn_bank* banks;        /* n_banks multiscale colour banks, each level accepted as by
+                                     mdn_plan_create (float16 7x7/7x7 levels on the column walk,
+                                     the levels of the tiled kernel with one launch per level and
+                                     tick, among them the paper's 4096-bucket configuration); the
                                      descriptors and thresholds are copied, the coefficient buffers
                                      must stay valid while the server lives */
     int32_t n_banks;              /* 1..16 */

@@ -129,14 +129,15 @@ namespace mdn {
 size_t batch_image_ws(int w, int h, int L, int storage) { return image_ws(w, h, L, storage) + al256((size_t)w * h); }
 
 size_t batch_table_bytes(int n, int L) {
-    return al256(sizeof(D2Image) * n) * L + al256(sizeof(SelImage) * n) * L + al256(sizeof(WalkImage) * n) * L;
+    return al256(sizeof(D2Image) * n) * L + al256(sizeof(SelImage) * n) * L + al256(sizeof(WalkImage) * n) * L +
+           al256(sizeof(TileImage) * n) * L;
 }
 
 // Per-level descriptors of one image's cascade, each with strip_begin = 0: d2[l] makes z^{l+1}
 // from z^l, sel[l] and walk[l] run level l (walk[0] writes `out`). ws (batch_image_ws bytes,
 // 256-aligned) holds z^1..z^L, u^1..u^{L-1} and the selector map, which every level reuses.
 void describe_cascade(const mdn_image& in, const mdn_image& out, void* ws, int L, int storage, const int (*rows)[3],
-                      int ncu, D2Image* d2, SelImage* sel, WalkImage* walk) {
+                      int ncu, D2Image* d2, SelImage* sel, WalkImage* walk, TileImage* tile) {
     mdn_image zl[kMaxLevels + 1], ul[kMaxLevels + 1];
     char* w = static_cast<char*>(ws);
     int W = in.width, H = in.height;
@@ -189,7 +190,30 @@ void describe_cascade(const mdn_image& in, const mdn_image& out, void* ws, int L
         walk[l].s_map = smap;
         walk[l].s_pitch = a.width;
         walk[l].rows = rows ? rows[l][2] : walk_rows(a.width, a.height, ncu * kWalkWaves);
+
+        if (tile) {
+            // the coarser output (z^L in RGB at the coarsest trained level) is also the image the
+            // coarse selector analyses
+            const mdn_image& c = l == L - 1 ? zl[L] : ul[l + 1];
+            const mdn_image& u = ul[l];
+            TileImage& t = tile[l];
+            memset(&t, 0, sizeof(t));
+            t.z = ImageArg{a.data, a.row_pitch, a.plane_pitch, a.width, a.height};
+            t.uc = ImageArg{c.data, c.row_pitch, c.plane_pitch, c.width, c.height};
+            t.su = t.uc;
+            t.out = u.data;
+            t.out_row = u.row_pitch;
+            t.out_plane = u.plane_pitch;
+            int ty = 0;
+            tiled_grid(a.width, a.height, &t.tiles_x, &ty);
+        }
     }
+}
+
+int tiles_of(const TileImage& t) {
+    int tx = 0, ty = 0;
+    tiled_grid(t.z.w, t.z.h, &tx, &ty);
+    return tx * ty;
 }
 
 int strips_of(const D2Image& d) { return d.nsx * ((d.Ho + d.rows - 1) / d.rows); }
@@ -206,9 +230,10 @@ mdn_status build_batch(const mdn_level* lv, const SelWalkArgs* selc, int L, int 
     std::vector<D2Image> d2((size_t)n * L);
     std::vector<SelImage> sel((size_t)n * L);
     std::vector<WalkImage> walk((size_t)n * L);
+    std::vector<TileImage> tile((size_t)n * L);
     for (int i = 0; i < n; ++i)
         describe_cascade(in[i], out[i], ws[i], L, storage, rows, ncu, &d2[(size_t)i * L], &sel[(size_t)i * L],
-                         &walk[(size_t)i * L]);
+                         &walk[(size_t)i * L], &tile[(size_t)i * L]);
     char* th = tab_host;
     char* td = tab_dev;
     for (int l = 0; l < L; ++l) {
@@ -259,6 +284,22 @@ mdn_status build_batch(const mdn_level* lv, const SelWalkArgs* selc, int L, int 
         th += al256(sizeof(WalkImage) * n);
         td += al256(sizeof(WalkImage) * n);
     }
+    for (int l = 0; l < L; ++l) {
+        TileImage* t = reinterpret_cast<TileImage*>(th);
+        int begin = 0;
+        for (int i = 0; i < n; ++i) {
+            t[i] = tile[(size_t)i * L + l];
+            t[i].tile_begin = begin;
+            begin += tiles_of(t[i]);
+        }
+        bl->tiled[l] = level_runs_tiled(lv[l], 3);
+        bl->lv[l] = lv[l];
+        bl->tiles[l] = reinterpret_cast<const TileImage*>(td);
+        bl->n_tiles[l] = begin;
+        th += al256(sizeof(TileImage) * n);
+        td += al256(sizeof(TileImage) * n);
+    }
+    bl->n_imgs = n;
     bl->L = L;
     bl->storage = storage;
     bl->in_dtype = in[0].dtype;
@@ -271,9 +312,14 @@ mdn_status launch_batch_level_d2(const BatchLaunch& b, int l, hipStream_t st) {
     return launch_down2_args(b.d2[l], 3, l == 0 ? b.in_dtype : b.storage, b.storage, st);
 }
 mdn_status launch_batch_level_sel(const BatchLaunch& b, int l, hipStream_t st) {
+    if (b.tiled[l]) return MDN_OK;                         // selection runs inside the tiled kernel
     return launch_select_args(b.sel[l], 3, l == 0 ? b.in_dtype : b.storage, st);
 }
 mdn_status launch_batch_level_walk(const BatchLaunch& b, int l, hipStream_t st) {
+    if (b.tiled[l])
+        return launch_select_apply_table(b.lv[l], b.tiles[l], b.n_imgs, b.n_tiles[l], 3, l == 0 ? b.in_dtype : b.storage,
+                                         b.storage, l == b.L - 1 ? MDN_RGB : MDN_YCC, l == 0 ? b.out_dtype : b.storage,
+                                         l == 0 ? MDN_RGB : MDN_YCC, st);
     return launch_walk_args(b.walk[l], l == 0 ? b.in_dtype : b.storage, b.storage, l == 0 ? b.out_dtype : b.storage, st);
 }
 
@@ -375,10 +421,12 @@ mdn_status mdn_plan_create(const mdn_bank* bank, int32_t storage, int32_t max_im
         mdn_status st = validate_level(&lv, 3);
         if (!st && !lv.t_s && lv.q_s > 1) st = fail(MDN_EINVAL, "plan: null thresholds");
         if (st) return st;
-        if (lv.coeff_dtype != MDN_F16 || !walk_supported(lv, 3))
-            return fail(MDN_ENOTSUP, "plan: the batched form runs float16 7x7/7x7 colour banks (K <= 243)");
-        if (lv.selector == MDN_SELECT_COARSE)
-            return fail(MDN_ENOTSUP, "plan: the batched form selects on each level's own input");
+        if (lv.radius_f < 1) return fail(MDN_ENOTSUP, "plan: the batched form runs multiscale banks");
+        const bool walk = lv.coeff_dtype == MDN_F16 && walk_supported(lv, 3);
+        if (walk && lv.selector == MDN_SELECT_COARSE)
+            return fail(MDN_ENOTSUP, "plan: float16 7x7/7x7 levels that select on the coarser output are not batched");
+        if (!walk && !level_runs_tiled(lv, 3))
+            return fail(MDN_ENOTSUP, "plan: float32 banks that fit in LDS one channel at a time are not batched");
     }
     mdn_status ist = init_walk_kernels();
     if (ist) return ist;
@@ -480,6 +528,11 @@ mdn_status mdn_plan_autotune(mdn_plan* p, const mdn_image* in, const mdn_image* 
         if (!st) st = run_d2(p, l);
     }
     for (int l = L - 1; l >= 0 && !st; --l) {
+        if (p->bl.tiled[l]) {
+            // fixed 64 x 16 tiles with the selection inline: nothing to tune, run the level once
+            st = run_walk(p, l);
+            continue;
+        }
         float best = 1e30f;
         for (int c : c_sel) {
             p->rows_sel[l] = c;

@@ -59,6 +59,8 @@ struct FilterArgs {
     double* feat_c;
     ImageArg su;                // coarse selector: the coarser output whose upsampling is analysed
     int32_t su_dtype, su_ycc;
+    const TileImage* imgs;      // batched launch: per-image fields (z, uc, su, out, maps), or null
+    int32_t n_imgs;
     SelectArg sel;
 };
 
@@ -145,10 +147,39 @@ __global__ __launch_bounds__(256) void k_select_apply(FilterArgs a) {
     UsRows* us = reinterpret_cast<UsRows*>(&pa[0][0]);
     __shared__ double ucs[SU ? C : 1][SU ? kCH : 1][SU ? kCW : 1];
 
+    // the image of this block: the launch's own, or (batched launches) the one whose tile range holds
+    // blockIdx.x, found by binary search over the image table
+    ImageArg Z = a.z, UC = a.uc, SUI = a.su;
+    void* OUT = a.out;
+    int64_t OROW = a.out_row, OPL = a.out_plane, SP = a.s_pitch;
+    const void* SIN = a.s_in;
+    void* SOUT = a.s_out;
+    int bx = blockIdx.x, by = blockIdx.y;
+    if (a.imgs != nullptr) {
+        const int t = blockIdx.x;
+        int lo = 0, hi = a.n_imgs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (a.imgs[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
+        }
+        const TileImage& ti = a.imgs[lo];
+        Z = ti.z;
+        UC = ti.uc;
+        SUI = ti.su;
+        OUT = ti.out;
+        OROW = ti.out_row;
+        OPL = ti.out_plane;
+        SIN = ti.s_in;
+        SOUT = ti.s_out;
+        SP = ti.s_pitch;
+        const int local = t - ti.tile_begin;
+        by = local / ti.tiles_x;
+        bx = local - by * ti.tiles_x;
+    }
     const int tid = threadIdx.x;
     const int tx = tid & 63, ty = tid >> 6;
-    const int x0 = blockIdx.x * kTW, y0 = blockIdx.y * kTH;
-    const int W = a.z.w, H = a.z.h;
+    const int x0 = bx * kTW, y0 = by * kTH;
+    const int W = Z.w, H = Z.h;
 
     // 1. stage the input window (clamped); the coarse selector without filtering never reads it
     if constexpr (!SU || APPLY) {
@@ -158,7 +189,7 @@ __global__ __launch_bounds__(256) void k_select_apply(FilterArgs a) {
             const int r = rem / kZW, q = rem - r * kZW;
             const int gy = clampi(y0 - kHalo + r, 0, H - 1);
             const int gx = clampi(x0 - kHalo + q, 0, W - 1);
-            zs[c][r][q] = load_any(a.z.data, a.z_dtype, (int64_t)c * a.z.plane + (int64_t)gy * a.z.row + gx);
+            zs[c][r][q] = load_any(Z.data, a.z_dtype, (int64_t)c * Z.plane + (int64_t)gy * Z.row + gx);
         }
     }
     const int cy0 = (y0 >> 1) - 3, cx0 = (x0 >> 1) - 3;
@@ -166,12 +197,12 @@ __global__ __launch_bounds__(256) void k_select_apply(FilterArgs a) {
         // the coarser output's window, float64 RGB (or grey), at clamped coarse positions
         for (int i = tid; i < kCH * kCW; i += 256) {
             const int r = i / kCW, q = i - r * kCW;
-            const int gy = clampi(cy0 + r, 0, a.su.h - 1);
-            const int gx = clampi(cx0 + q, 0, a.su.w - 1);
-            const int64_t off = (int64_t)gy * a.su.row + gx;
+            const int gy = clampi(cy0 + r, 0, SUI.h - 1);
+            const int gx = clampi(cx0 + q, 0, SUI.w - 1);
+            const int64_t off = (int64_t)gy * SUI.row + gx;
             double v[C];
 #pragma unroll
-            for (int c = 0; c < C; ++c) v[c] = (double)load_any(a.su.data, a.su_dtype, off + (int64_t)c * a.su.plane);
+            for (int c = 0; c < C; ++c) v[c] = (double)load_any(SUI.data, a.su_dtype, off + (int64_t)c * SUI.plane);
             if constexpr (C == 3) {
                 if (a.su_ycc) ycc_to_rgb_d(v[0], v[1], v[2]);
             }
@@ -183,7 +214,7 @@ __global__ __launch_bounds__(256) void k_select_apply(FilterArgs a) {
 
     // 2. selector
     int sv[4];
-    if (a.s_in == nullptr) {
+    if (SIN == nullptr) {
         for (int i = tid; i < kPH * kPW; i += 256) {
             const int r = i / kPW, q = i - r * kPW;
             const int yc = clampi(y0 - 2 + r, 0, H - 1);
@@ -196,7 +227,7 @@ __global__ __launch_bounds__(256) void k_select_apply(FilterArgs a) {
             double A = 0.0, B = 0.0, Cc = 0.0;
             if constexpr (SU) {
                 // linear factor-two upsampling of the coarse window at fine (fy, fx), both clamped
-                const int Hc = a.su.h, Wc = a.su.w;
+                const int Hc = SUI.h, Wc = SUI.w;
                 auto up = [&](int c, int fy, int fx) {
                     const int my = fy >> 1, mx = fx >> 1;
                     const int ny = (fy & 1) ? min(my + 1, Hc - 1) : max(my - 1, 0);
@@ -218,7 +249,7 @@ __global__ __launch_bounds__(256) void k_select_apply(FilterArgs a) {
                 }
             } else if (C == 3 && a.sel.luma) {
                 // luma-only structure tensor: gradients of Y at the four neighbours
-                auto Y = [&](int yy, int xx) { return luma_d(zs[0][yy][xx], zs[1][yy][xx], zs[C - 1][yy][xx]); };
+                auto Y = [&](int yy, int xx) { return luma_d(zs[0][yy][xx], zs[C > 1 ? 1 : 0][yy][xx], zs[C - 1][yy][xx]); };
                 const double gx = (Y(ly, lxr) - Y(ly, lxl)) * 0.5;
                 const double gy = (Y(lyd, lx) - Y(lyu, lx)) * 0.5;
                 A = gx * gx;
@@ -299,20 +330,20 @@ __global__ __launch_bounds__(256) void k_select_apply(FilterArgs a) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int y = y0 + ty + 4 * k, x = x0 + tx;
-            const int64_t o = (int64_t)y * a.s_pitch + x;
-            sv[k] = (y < H && x < W) ? (a.s16 ? (int)static_cast<const uint16_t*>(a.s_in)[o]
-                                              : (int)static_cast<const uint8_t*>(a.s_in)[o])
+            const int64_t o = (int64_t)y * SP + x;
+            sv[k] = (y < H && x < W) ? (a.s16 ? (int)static_cast<const uint16_t*>(SIN)[o]
+                                              : (int)static_cast<const uint8_t*>(SIN)[o])
                                      : 0;
         }
     }
-    if (a.s_out != nullptr) {
+    if (SOUT != nullptr) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int y = y0 + ty + 4 * k, x = x0 + tx;
-            const int64_t o = (int64_t)y * a.s_pitch + x;
+            const int64_t o = (int64_t)y * SP + x;
             if (y < H && x < W) {
-                if (a.s16) static_cast<uint16_t*>(a.s_out)[o] = (uint16_t)sv[k];
-                else static_cast<uint8_t*>(a.s_out)[o] = (uint8_t)sv[k];
+                if (a.s16) static_cast<uint16_t*>(SOUT)[o] = (uint16_t)sv[k];
+                else static_cast<uint8_t*>(SOUT)[o] = (uint8_t)sv[k];
             }
         }
     }
@@ -334,12 +365,12 @@ __global__ __launch_bounds__(256) void k_select_apply(FilterArgs a) {
         const int cy0 = y0 / 2 - RF, cx0 = x0 / 2 - RF;
         for (int i = tid; i < kUH * kUW; i += 256) {
             const int r = i / kUW, q = i - r * kUW;
-            const int gy = clampi(cy0 + r, 0, a.uc.h - 1);
-            const int gx = clampi(cx0 + q, 0, a.uc.w - 1);
-            const int64_t off = (int64_t)gy * a.uc.row + gx;
+            const int gy = clampi(cy0 + r, 0, UC.h - 1);
+            const int gx = clampi(cx0 + q, 0, UC.w - 1);
+            const int64_t off = (int64_t)gy * UC.row + gx;
             float v[C];
 #pragma unroll
-            for (int c = 0; c < C; ++c) v[c] = load_any(a.uc.data, a.uc_dtype, off + (int64_t)c * a.uc.plane);
+            for (int c = 0; c < C; ++c) v[c] = load_any(UC.data, a.uc_dtype, off + (int64_t)c * UC.plane);
             if constexpr (C == 3) {
                 if (a.uc_rgb) Ycc::from_rgb(v[0], v[1], v[2], v[0], v[1], v[2]);
             }
@@ -382,12 +413,12 @@ __global__ __launch_bounds__(256) void k_select_apply(FilterArgs a) {
                 acc[c] = sum;
             }
         }
-        const int64_t off = (int64_t)y * a.out_row + x;
+        const int64_t off = (int64_t)y * OROW + x;
         if constexpr (C == 3) {
             if (a.out_rgb) Ycc::to_rgb(acc[0], acc[1], acc[2], acc[0], acc[1], acc[2]);
         }
 #pragma unroll
-        for (int c = 0; c < C; ++c) store_any(a.out, a.out_dtype, off + (int64_t)c * a.out_plane, acc[c]);
+        for (int c = 0; c < C; ++c) store_any(OUT, a.out_dtype, off + (int64_t)c * OPL, acc[c]);
     }
 }
 
@@ -496,6 +527,49 @@ void orientation_boundaries(int q_theta, double* bcos, double* bsin) {
         bcos[k - 1] = k < m ? c : -c;
         bsin[k - 1] = s;
     }
+}
+
+void tiled_grid(int w, int h, int* tiles_x, int* tiles_y) {
+    *tiles_x = (w + kTW - 1) / kTW;
+    *tiles_y = (h + kTH - 1) / kTH;
+}
+
+bool level_runs_tiled(const mdn_level& lvl, int channels) {
+    if (lvl.radius_f < 1) return true;                       // single scale
+    if (lvl.coeff_dtype == MDN_F16 && walk_supported(lvl, channels)) return false;
+    return wide_selector(lvl) || !apply_lds_supported(lvl, channels);
+}
+
+mdn_status launch_select_apply_table(const mdn_level& lvl, const TileImage* imgs, int n_imgs, int n_tiles, int C,
+                                     int z_dtype, int uc_dtype, int uc_color, int out_dtype, int out_color,
+                                     hipStream_t st) {
+    if (n_tiles <= 0) return MDN_OK;
+    FilterArgs fa;
+    memset(&fa, 0, sizeof(fa));
+    fa.imgs = imgs;
+    fa.n_imgs = n_imgs;
+    fa.z_dtype = z_dtype;
+    fa.uc_dtype = uc_dtype;
+    fa.uc_rgb = uc_color == MDN_RGB;
+    fa.out_dtype = out_dtype;
+    fa.out_rgb = out_color == MDN_RGB;
+    fa.s16 = wide_selector(lvl);
+    fa.coeffs = lvl.coeffs;
+    fa.K = level_buckets(lvl);
+    fill_select_arg(lvl, fa.sel);
+    const bool su = lvl.selector == MDN_SELECT_COARSE;
+    if (su) {
+        fa.su_dtype = uc_dtype;
+        fa.su_ycc = uc_color == MDN_YCC;
+    }
+    const int rf = lvl.radius_f < 0 ? -1 : lvl.radius_f;
+    // one block per tile: a grid of n_tiles x 1 tiles
+    const int w = n_tiles * kTW, h = 1;
+    if (C == 3 && lvl.coeff_dtype == MDN_F32) return dispatch_radii<3, float>(fa, true, su, rf, lvl.radius_g, w, h, st);
+    if (C == 3 && lvl.coeff_dtype == MDN_F16) return dispatch_radii<3, __half>(fa, true, su, rf, lvl.radius_g, w, h, st);
+    if (C == 1 && lvl.coeff_dtype == MDN_F32) return dispatch_radii<1, float>(fa, true, su, rf, lvl.radius_g, w, h, st);
+    if (C == 1 && lvl.coeff_dtype == MDN_F16) return dispatch_radii<1, __half>(fa, true, su, rf, lvl.radius_g, w, h, st);
+    return fail(MDN_EINVAL, "unsupported channels/coeff dtype");
 }
 
 mdn_status launch_select_apply(const mdn_image& z, const mdn_image* uc, const void* s_in, int64_t s_pitch,

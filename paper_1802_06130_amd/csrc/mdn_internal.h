@@ -109,6 +109,28 @@ mdn_status launch_select_apply(const mdn_image& z, const mdn_image* uc, const vo
                                int64_t s_pitch, void* s_out, const mdn_level& lvl,
                                const mdn_image* out, hipStream_t st);
 
+// One image of a batched launch of the tiled select-and-filter kernel (the kernel of the levels
+// that run neither the column walk nor the LDS-bank kernel): its 64 x 16 output tiles are the
+// launch's tiles [tile_begin, tile_begin + tiles_x * ceil(h / 16)).
+struct TileImage {
+    ImageArg z, uc, su;         // level input (RGB), coarser output, image the selector analyses
+    void* out;
+    int64_t out_row, out_plane;
+    const void* s_in;           // selector map to filter with, or null (select inline)
+    void* s_out;                // receives the selector used, or null
+    int64_t s_pitch;
+    int32_t tiles_x, tile_begin;
+};
+// tiles across and down of a w x h level for the tiled kernel
+void tiled_grid(int w, int h, int* tiles_x, int* tiles_y);
+// Batched launch over `n_imgs` images (device table, `n_tiles` tiles in all) of one level: the
+// colours and dtypes are those of the launch, as for launch_select_apply.
+mdn_status launch_select_apply_table(const mdn_level& lvl, const TileImage* imgs, int n_imgs, int n_tiles, int C,
+                                     int z_dtype, int uc_dtype, int uc_color, int out_dtype, int out_color,
+                                     hipStream_t st);
+// true when the cascade filters this level with the tiled kernel (selection inline, no map)
+bool level_runs_tiled(const mdn_level& lvl, int channels);
+
 bool walk_supported(const mdn_level& lvl, int channels);
 // Multiscale levels whose bank, one channel at a time, fits in LDS beside the tile windows
 // (colour levels; float32 7x7/7x7 banks up to 219 buckets) filter from a selector map with the bank in LDS.

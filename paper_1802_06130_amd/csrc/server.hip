@@ -101,6 +101,7 @@ struct Bank {
     mdn_level lv[kMaxLevels];
     double thr[kMaxLevels][2][kMaxThr];
     SelWalkArgs selc[kMaxLevels];
+    bool tiled[kMaxLevels];    // level filtered by the tiled kernel (selection inline, one launch)
 };
 
 struct Request {
@@ -122,6 +123,7 @@ struct Request {
     D2Image d2[kMaxLevels];
     SelImage sel[kMaxLevels];
     WalkImage walk[kMaxLevels];
+    TileImage tile[kMaxLevels];
     int64_t px[kMaxLevels + 1];
 };
 
@@ -142,8 +144,9 @@ struct GroupKey {
     }
 };
 
+// Levels of a tiled bank level have no selection launch: the tiled kernel selects inline.
 template <typename F>
-void for_each_group(const std::vector<Item>& items, int round, int storage, F&& f) {
+void for_each_group(const std::vector<Item>& items, int round, int storage, const Bank* banks, F&& f) {
     std::map<GroupKey, std::vector<const Item*>> g;
     for (const Item& it : items) {
         if (it.round != round) continue;
@@ -154,7 +157,7 @@ void for_each_group(const std::vector<Item>& items, int round, int storage, F&& 
             g[{0, 0, 0, level_dtype(r, l, storage), storage}].push_back(&it);
         } else {
             const int l = 2 * L - 1 - it.stage;
-            g[{1, r.q.bank, l, level_dtype(r, l, storage), 0}].push_back(&it);
+            if (!banks[r.q.bank].tiled[l]) g[{1, r.q.bank, l, level_dtype(r, l, storage), 0}].push_back(&it);
             g[{2, r.q.bank, l, level_dtype(r, l, storage), level_dtype(r, l, storage)}].push_back(&it);
         }
     }
@@ -209,7 +212,8 @@ public:
                         (unsigned long long)c.hbm_budget);
         // one table region per tick that can be in flight, plus one being filled
         const size_t items = (size_t)c.max_slots * c.stages_per_tick;
-        tab_cap_ = items * (sizeof(D2Image) + sizeof(SelImage) + sizeof(WalkImage)) + 3 * 256 * (items + 4);
+        tab_cap_ = items * (sizeof(D2Image) + sizeof(SelImage) + sizeof(WalkImage) + sizeof(TileImage)) +
+                   3 * 256 * (items + 4);
         const int ring = c.max_ticks_in_flight + 1;
         tab_host_.assign(ring, nullptr);
         tab_dev_.assign(ring, nullptr);
@@ -246,7 +250,7 @@ public:
         a.plane_pitch = (int64_t)r.q.width * r.q.height;
         b = a;
         b.data = out;
-        describe_cascade(a, b, ws, r.L, storage_, nullptr, ncu_, r.d2, r.sel, r.walk);
+        describe_cascade(a, b, ws, r.L, storage_, nullptr, ncu_, r.d2, r.sel, r.walk, r.tile);
     }
 
     void* staging(int slot) override { return staging_.empty() ? nullptr : staging_[slot]; }
@@ -269,7 +273,7 @@ public:
         };
         std::vector<Launch> ls;
         for (int round = 0; round < rounds; ++round) {
-            for_each_group(items, round, storage_, [&](const GroupKey& k, const std::vector<const Item*>& its) {
+            for_each_group(items, round, storage_, banks_, [&](const GroupKey& k, const std::vector<const Item*>& its) {
                 Launch L{k, used, (int)its.size(), 0, {}};
                 int begin = 0;
                 auto put = [&](const void* d, size_t n) {
@@ -288,6 +292,11 @@ public:
                         SelImage d = r.sel[l];
                         d.strip_begin = begin;
                         begin += strips_of(d);
+                        put(&d, sizeof(d));
+                    } else if (banks_[k.bank].tiled[l]) {
+                        TileImage d = r.tile[l];
+                        d.tile_begin = begin;
+                        begin += tiles_of(d);
                         put(&d, sizeof(d));
                     } else {
                         WalkImage d = r.walk[l];
@@ -321,6 +330,11 @@ public:
                 a.n_imgs = L.n;
                 a.n_strips = L.strips;
                 st = launch_select_args(a, 3, L.k.zd, comp_);
+            } else if (bk.tiled[L.k.level]) {
+                const int l = L.k.level;
+                st = launch_select_apply_table(bk.lv[l], reinterpret_cast<const TileImage*>(td + L.off), L.n, L.strips, 3,
+                                               L.k.zd, storage_, l == bk.L - 1 ? MDN_RGB : MDN_YCC, L.k.od,
+                                               l == 0 ? MDN_RGB : MDN_YCC, comp_);
             } else {
                 const mdn_level& lv = bk.lv[L.k.level];
                 WalkArgs a;
@@ -408,7 +422,8 @@ private:
 // about P / rate (pyramid stages 0.075, selection and filtering 0.675 of their level's pixels).
 class FakeExecutor final : public Executor {
 public:
-    mdn_status init(const mdn_server_config& c, const Bank*) override {
+    mdn_status init(const mdn_server_config& c, const Bank* banks) override {
+        banks_ = banks;
         storage_ = c.storage;
         h2d_ = c.fake_h2d_gbps > 0 ? c.fake_h2d_gbps * 1e9 : 25e9;
         d2h_ = c.fake_d2h_gbps > 0 ? c.fake_d2h_gbps * 1e9 : 25e9;
@@ -433,7 +448,7 @@ public:
         double work = 0.0, stall = 0.0;
         bool async_fail = false;
         for (int round = 0; round < rounds; ++round)
-            for_each_group(items, round, storage_, [&](const GroupKey&, const std::vector<const Item*>& its) {
+            for_each_group(items, round, storage_, banks_, [&](const GroupKey&, const std::vector<const Item*>& its) {
                 ++n;
                 for (const Item* it : its) {
                     Request& r = *it->r;
@@ -505,6 +520,7 @@ private:
         toks_[next_] = Tok{done, f};
         return next_++;
     }
+    const Bank* banks_ = nullptr;
     int storage_ = MDN_F16;
     double h2d_ = 0, d2h_ = 0, rate_ = 0, launch_ = 0;
     double clock_ = 0, h2d_free_ = 0, d2h_free_ = 0, comp_free_ = 0;
@@ -843,10 +859,13 @@ mdn_status mdn_server_create(const mdn_server_config* cfg, mdn_server** out) {
             mdn_status e = validate_level(&lv, 3);
             if (!e && !lv.t_s && lv.q_s > 1) e = fail(MDN_EINVAL, "server: null thresholds");
             if (e) return e;
-            if (lv.coeff_dtype != MDN_F16 || !walk_supported(lv, 3))
-                return fail(MDN_ENOTSUP, "server: banks must be float16 7x7/7x7 colour banks (K <= 243)");
-            if (lv.selector == MDN_SELECT_COARSE)
-                return fail(MDN_ENOTSUP, "server: banks must select on each level's own input");
+            if (lv.radius_f < 1) return fail(MDN_ENOTSUP, "server: banks must be multiscale");
+            const bool walk = lv.coeff_dtype == MDN_F16 && walk_supported(lv, 3);
+            if (walk && lv.selector == MDN_SELECT_COARSE)
+                return fail(MDN_ENOTSUP, "server: float16 7x7/7x7 levels that select on the coarser output are not served");
+            if (!walk && !level_runs_tiled(lv, 3))
+                return fail(MDN_ENOTSUP, "server: float32 banks that fit in LDS one channel at a time are not served");
+            B.tiled[l] = !walk;
             B.lv[l] = lv;
             for (int j = 0; j < lv.q_s - 1; ++j) B.thr[l][0][j] = lv.t_s[j];
             for (int j = 0; j < lv.q_c - 1; ++j) B.thr[l][1][j] = lv.t_c[j];

@@ -12,7 +12,10 @@
 // up to kMaxSeg equal segments of whole 64-sample chunks, so that large buckets do not leave the
 // rest of the device idle. A workgroup gathers 64 samples at a time into LDS as a feature-major
 // matrix X^T (regression taps followed by the target value(s), zero padded to a multiple of 32;
-// the gathers of the next chunk are in flight while the current one is multiplied),
+// the gathers of the next chunk are in flight while the current one is multiplied). The planes
+// are float32 copies with a replicated margin of kPad pixels, so every tap row of a sample is
+// consecutive floats of one plane row: a wave takes whole tap rows, one sample per lane, each
+// row one contiguous load,
 // and accumulates the upper-triangle 32x32 tiles of X^T X on MFMA with FP32 accumulators. The
 // target value rides along as an extra feature, so the same tiles yield G = sum x x^T,
 // b = sum x y and yy = sum y^2. Two products are offered:
@@ -42,6 +45,8 @@ typedef float f16v __attribute__((ext_vector_type(16)));
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 
 constexpr int kChunk = 64;                 // samples per MFMA chunk
+constexpr int kPad = 3;                    // replicated margin of the gather planes (radius <= 3)
+constexpr int kMaxRows = 24;               // tap rows per sample: 3 planes x 7 rows + 3 targets
 constexpr int kMaxSeg = 16;                // segments per bucket run
 constexpr int kMinSegChunks = 8;           // chunks per segment, at least
 
@@ -63,14 +68,16 @@ int gram_segments(int64_t npx, int K) {
     return (int)(s < 1 ? 1 : (s > cap ? cap : s));
 }
 
-// feature descriptor: source (0 fine, 1 coarse, 2 target), plane, dy, dx
-__host__ __device__ inline int feat_pack(int src, int plane, int dy, int dx) {
-    return (src << 24) | (plane << 16) | ((dy + 128) << 8) | (dx + 128);
+// tap-row descriptor: source (0 fine, 1 coarse, 2 target), plane, row offset dy, first column
+// offset dx0, length, index of its first feature
+__host__ __device__ inline int row_pack(int src, int plane, int dy, int dx0, int len, int fbase) {
+    return (src << 28) | (plane << 26) | ((dy + 8) << 22) | ((dx0 + 8) << 18) | (len << 14) | fbase;
 }
 
 struct GramArgs {
     // YCbCr (or grey) planes of z^l, of the clean level u^l and of the coarser output u^{l+1},
-    // float32, in one buffer: target and coarse planes start at the given element offsets
+    // float32 with a replicated margin of kPad pixels on every side, in one buffer: target and
+    // coarse planes start at the given element offsets; pitches are those of the padded planes
     const float* planes;
     int32_t target_off, coarse_off;
     int32_t f_row, f_plane, c_row, c_plane;
@@ -79,7 +86,8 @@ struct GramArgs {
     const int32_t* off;     // [K+1] start of each bucket's run in idx
     int32_t D, Daug, nrhs, per_channel;
     int32_t nseg;           // segments per bucket run
-    int32_t feat[kMaxFeat];
+    int32_t nrows;          // tap rows per sample
+    int32_t rows[kMaxRows];
     float* part;            // [K][systems per bucket][nseg][tiles][1024] partial tiles
     double* G;
     double* b;
@@ -87,12 +95,8 @@ struct GramArgs {
     double* yy;
 };
 
-// float -> bfloat16, round to nearest even (inputs are finite).
-__device__ __forceinline__ __bf16 to_bf16(float v) {
-    const uint32_t u = __float_as_uint(v);
-    const uint32_t r = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
-    return __builtin_bit_cast(__bf16, (unsigned short)r);
-}
+// float -> bfloat16, round to nearest even (v_cvt_pk_bf16_f32 on gfx950; inputs are finite).
+__device__ __forceinline__ __bf16 to_bf16(float v) { return (__bf16)v; }
 
 __device__ __forceinline__ float from_bf16(__bf16 h) {
     return __uint_as_float((uint32_t)__builtin_bit_cast(unsigned short, h) << 16);
@@ -109,7 +113,45 @@ __host__ __device__ inline void tile_pq(int T, int t, int* P, int* Q) {
     *Q = p + t;
 }
 
-template <int PREC, int T>
+// Sum the segment partials of one system in segment order (float64) and add them to the
+// accumulators (256 threads); the result does not depend on timing.
+__device__ void add_partials(const GramArgs& a, int T, int k, int sys_c, int sys, int nseg) {
+    const int NT = T * (T + 1) / 2;
+    if (sys_c == 0 && threadIdx.x == 0) a.n[k] += a.off[k + 1] - a.off[k];
+    const float* part = a.part + (int64_t)sys * a.nseg * NT * 1024;
+    const int D = a.D;
+    double* G = a.G + (int64_t)sys * D * D;
+    double* bvec = a.b + (int64_t)sys * a.nrhs * D;
+    double* yy = a.yy + (int64_t)sys * a.nrhs;
+    for (int e = threadIdx.x; e < NT * 1024; e += 256) {
+        // every segment's partial is loaded at once (idle segments re-read segment 0), then
+        // summed in segment order
+        float pv[kMaxSeg];
+#pragma unroll
+        for (int sg = 0; sg < kMaxSeg; ++sg) pv[sg] = part[(int64_t)(sg < nseg ? sg : 0) * NT * 1024 + e];
+        double v = 0.0;
+#pragma unroll
+        for (int sg = 0; sg < kMaxSeg; ++sg)
+            if (sg < nseg) v += (double)pv[sg];
+        const int t = e >> 10, r = (e >> 6) & 15, lane = e & 63;
+        int P, Q;
+        tile_pq(T, t, &P, &Q);
+        const int p = P * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int q = Q * 32 + (lane & 31);
+        if (p >= a.Daug || q >= a.Daug) continue;
+        if (p < D && q < D) {
+            G[(int64_t)p * D + q] += v;
+            if (P != Q) G[(int64_t)q * D + p] += v;
+        } else if (p < D && q >= D) {
+            bvec[(int64_t)(q - D) * D + p] += v;
+        } else if (p >= D && q >= D && p == q) {
+            yy[p - D] += v;
+        }
+    }
+}
+
+// RPW: tap rows per wave (the sample's rows are dealt to the four waves), at least ceil(nrows / 4).
+template <int PREC, int T, int RPW>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_gram(GramArgs a) {
     constexpr int DPAD = 32 * T;
     constexpr int NT = T * (T + 1) / 2;
@@ -118,14 +160,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
     using XT = typename std::conditional<PREC == 0, float, __bf16>::type;
     __shared__ XT xhi[DPAD][LDW];
     __shared__ XT xlo[PREC == 0 ? 1 : DPAD][PREC == 0 ? 1 : LDW];
-    __shared__ int feat[kMaxFeat];
-
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: row decoding is scalar
     const int k = blockIdx.x;
     const int sys_c = blockIdx.y;                      // channel (per-channel systems) or 0
     const int seg = blockIdx.z;
     const int plane_off = a.per_channel ? sys_c : 0;
-    const int W = a.W, H = a.H;
+    const int W = a.W;
 
     // this segment's chunks of the bucket's run
     const int beg = a.off[k], end = a.off[k + 1];
@@ -134,16 +175,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
     const int c0 = seg * per, c1 = min(chunks, c0 + per);
     if (c0 >= c1) return;
 
-    // launch constants as wave-uniform values (selected arithmetically in the gather)
     const float* planes = a.planes;
-    const int target_off = __builtin_amdgcn_readfirstlane(a.target_off);
-    const int coarse_off = __builtin_amdgcn_readfirstlane(a.coarse_off);
-    const int f_row = __builtin_amdgcn_readfirstlane(a.f_row), f_plane = __builtin_amdgcn_readfirstlane(a.f_plane);
-    const int c_row = __builtin_amdgcn_readfirstlane(a.c_row), c_plane = __builtin_amdgcn_readfirstlane(a.c_plane);
-    const int h1 = H - 1, w1 = W - 1;
-    const int hc1 = __builtin_amdgcn_readfirstlane(a.Hc - 1), wc1 = __builtin_amdgcn_readfirstlane(a.Wc - 1);
+    const int nrows = __builtin_amdgcn_readfirstlane(a.nrows);
     const int daug = __builtin_amdgcn_readfirstlane(a.Daug);
-    for (int f = tid; f < kMaxFeat; f += 256) feat[f] = f < daug ? a.feat[f] : 0;
+    // feature rows past the last feature stay zero
+    for (int e = tid; e < (DPAD - daug) * LDW; e += 256) {
+        const int f = daug + e / LDW, col = e - (e / LDW) * LDW;
+        xhi[f][col] = XT(0.0f);
+        if constexpr (PREC != 0) xlo[f][col] = XT(0.0f);
+    }
 
     // tiles owned by this wave: t = wave, wave + 4, ...
     int tP[TPW], tQ[TPW];
@@ -156,49 +196,63 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[i][r] = 0.0f;
 
-    // Gather: four threads share a sample and take every fourth feature. All loads of a chunk
-    // are issued at once (branch-free addressing from one base pointer; lanes without a sample
-    // or feature read element 0) and consumed only when the chunk is stored to LDS.
-    constexpr int kPer = DPAD / 4;
-    static_assert(kPer <= 64, "sample mask holds 64 features per thread");
-    const int sp = tid >> 2, sq = tid & 3;
-    float v[kPer];
-    uint64_t okm = 0;
-    auto load = [&](int chunk) {
+    // Gather: wave w takes tap rows w, w + 4, ... of every sample, one sample per lane; a row's
+    // taps are consecutive floats of a padded plane row, loaded together. The next chunk's loads
+    // are in flight while the current chunk is multiplied from LDS, and are consumed only when
+    // that chunk is stored to LDS. (Two chunks in flight measured the same.)
+    struct Buf {
+        float v[RPW][8];
+        bool live;
+    };
+    Buf buf;
+    auto load = [&](int chunk, Buf& b) {
         const int base = beg + chunk * kChunk;
-        const bool live = base + sp < end;
-        const int pix = live ? a.idx[base + sp] : 0;
-        const int y = pix / W, x = pix - (pix / W) * W;
-        okm = 0;
+        b.live = base + lane < end;
+        const int pix = b.live ? a.idx[base + lane] : 0;
+        const int y = pix / W, x = pix - y * W;
+        float (&v)[RPW][8] = b.v;
 #pragma unroll
-        for (int j = 0; j < kPer; ++j) {
-            const int f = sq + 4 * j;
-            const bool ok = live && f < daug;
-            const int e = feat[f < kMaxFeat ? f : 0];
-            const int src = e >> 24, pl = ((e >> 16) & 0xff) + plane_off;
-            const int dy = ((e >> 8) & 0xff) - 128, dx = (e & 0xff) - 128;
+        for (int i = 0; i < RPW; ++i) {
+            const int r = wave + 4 * i;
+            if (r >= nrows) break;
+            const int e = a.rows[r];
+            const int src = e >> 28, pl = ((e >> 26) & 3) + plane_off;
+            const int dy = ((e >> 22) & 15) - 8, dx0 = ((e >> 18) & 15) - 8, len = (e >> 14) & 15;
             const bool cs = src == 1;
-            const int yb = cs ? (y >> 1) : y, xb = cs ? (x >> 1) : x;
-            const int hm = cs ? hc1 : h1, wm = cs ? wc1 : w1;
-            const int row = cs ? c_row : f_row, pls = cs ? c_plane : f_plane;
-            const int start = src == 0 ? 0 : (cs ? coarse_off : target_off);
-            const int o = start + pl * pls + clampi(yb + dy, 0, hm) * row + clampi(xb + dx, 0, wm);
-            v[j] = planes[ok ? o : 0];
-            okm |= (uint64_t)ok << j;
+            const int yb = (cs ? (y >> 1) : y) + kPad + dy, xb = (cs ? (x >> 1) : x) + kPad + dx0;
+            const int start = src == 0 ? 0 : (cs ? a.coarse_off : a.target_off);
+            const float* q = planes + start + pl * (cs ? a.c_plane : a.f_plane) + yb * (cs ? a.c_row : a.f_row) + xb;
+            // the row length is the same on every lane (wave-uniform branch)
+            if (len == 7) {
+                __builtin_memcpy(&v[i][0], q, 7 * sizeof(float));
+            } else if (len == 5) {
+                __builtin_memcpy(&v[i][0], q, 5 * sizeof(float));
+            } else if (len == 3) {
+                __builtin_memcpy(&v[i][0], q, 3 * sizeof(float));
+            } else {
+                v[i][0] = *q;
+            }
         }
         __builtin_amdgcn_sched_barrier(0);   // keep every load ahead of the first use
     };
-    auto store = [&]() {
+    auto store = [&](const Buf& b) {
 #pragma unroll
-        for (int j = 0; j < kPer; ++j) {
-            const int f = sq + 4 * j;
-            const float w = (okm >> j) & 1ull ? v[j] : 0.0f;
-            if constexpr (PREC == 0) {
-                xhi[f][sp] = w;
-            } else {
-                const __bf16 h = to_bf16(w);
-                xhi[f][sp] = h;
-                xlo[f][sp] = to_bf16(w - from_bf16(h));
+        for (int i = 0; i < RPW; ++i) {
+            const int r = wave + 4 * i;
+            if (r >= nrows) break;
+            const int e = a.rows[r];
+            const int len = (e >> 14) & 15, fb = e & 0x3fff;
+#pragma unroll
+            for (int j = 0; j < 7; ++j) {
+                if (j >= len) break;
+                const float w = b.live ? b.v[i][j] : 0.0f;
+                if constexpr (PREC == 0) {
+                    xhi[fb + j][lane] = w;
+                } else {
+                    const __bf16 h = to_bf16(w);
+                    xhi[fb + j][lane] = h;
+                    xlo[fb + j][lane] = to_bf16(w - from_bf16(h));
+                }
             }
         }
     };
@@ -232,17 +286,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
         }
     };
 
-    __syncthreads();                 // feature table
-    load(c0);
-    store();
+    load(c0, buf);
+    store(buf);
     __syncthreads();
     for (int c = c0; c < c1; ++c) {
         const bool more = c + 1 < c1;
-        if (more) load(c + 1);       // in flight during the products
+        if (more) load(c + 1, buf);  // in flight during the products
         multiply();
         __syncthreads();             // every wave is done with this chunk
         if (more) {
-            store();
+            store(buf);
             __syncthreads();
         }
     }
@@ -260,55 +313,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
 }
 
 // Sum the segment partials of each system in segment order (float64) and add them to the
-// accumulators; the result does not depend on timing.
+// accumulators; the result does not depend on timing. (Letting the last segment of each system
+// do this inside k_gram was measured 2.4x slower: every workgroup's device-scope release and
+// acquire wrote back and invalidated its XCD's L2, which the sample gathers depend on.)
 __global__ __launch_bounds__(256) void k_gram_reduce(GramArgs a, int T) {
-    const int NT = T * (T + 1) / 2;
     const int k = blockIdx.x, sys_c = blockIdx.y;
     const int sys = a.per_channel ? k * (int)gridDim.y + sys_c : k;
-    const int beg = a.off[k], end = a.off[k + 1];
-    const int chunks = (end - beg + kChunk - 1) / kChunk;
+    const int chunks = (a.off[k + 1] - a.off[k] + kChunk - 1) / kChunk;
     const int per = seg_chunks(chunks, a.nseg);
     const int nseg = (chunks + per - 1) / per;                      // segments that ran
-    if (sys_c == 0 && threadIdx.x == 0) a.n[k] += end - beg;
-    const float* part = a.part + (int64_t)sys * a.nseg * NT * 1024;
-    const int D = a.D;
-    double* G = a.G + (int64_t)sys * D * D;
-    double* bvec = a.b + (int64_t)sys * a.nrhs * D;
-    double* yy = a.yy + (int64_t)sys * a.nrhs;
-    if (nseg == 0) return;
-    for (int e = threadIdx.x; e < NT * 1024; e += 256) {
-        // every segment's partial is loaded at once (idle segments re-read segment 0), then
-        // summed in segment order
-        float pv[kMaxSeg];
-#pragma unroll
-        for (int sg = 0; sg < kMaxSeg; ++sg) pv[sg] = part[(int64_t)(sg < nseg ? sg : 0) * NT * 1024 + e];
-        double v = 0.0;
-#pragma unroll
-        for (int sg = 0; sg < kMaxSeg; ++sg)
-            if (sg < nseg) v += (double)pv[sg];
-        const int t = e >> 10, r = (e >> 6) & 15, lane = e & 63;
-        int P, Q;
-        tile_pq(T, t, &P, &Q);
-        const int p = P * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        const int q = Q * 32 + (lane & 31);
-        if (p >= a.Daug || q >= a.Daug) continue;
-        if (p < D && q < D) {
-            G[(int64_t)p * D + q] += v;
-            if (P != Q) G[(int64_t)q * D + p] += v;
-        } else if (p < D && q >= D) {
-            bvec[(int64_t)(q - D) * D + p] += v;
-        } else if (p >= D && q >= D && p == q) {
-            yy[p - D] += v;
-        }
-    }
+    if (nseg == 0) return;                                            // empty bucket: nothing to add
+    add_partials(a, T, k, sys_c, sys, nseg);
 }
 
-// float32 YCbCr (or grey) planes of an RGB / grey image, for the sample gathers.
+// float32 YCbCr (or grey) planes of an RGB / grey image for the sample gathers, with a margin of
+// kPad pixels on every side holding the clamped (replicated) border: padded element (y, x),
+// -kPad <= y < h + kPad and -kPad <= x < w + kPad, is at out[(y + kPad) o_row + x + kPad].
 __global__ void k_to_planes(ImageArg in, int32_t dtype, int32_t rgb_to_ycc, int32_t C, float* out, int64_t o_row,
                             int64_t o_plane) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y;
-    if (x >= in.w || y >= in.h) return;
+    const int xp = blockIdx.x * blockDim.x + threadIdx.x;
+    const int yp = blockIdx.y;
+    if (xp >= in.w + 2 * kPad || yp >= in.h + 2 * kPad) return;
+    const int x = clampi(xp - kPad, 0, in.w - 1), y = clampi(yp - kPad, 0, in.h - 1);
     const int64_t off = (int64_t)y * in.row + x;
     float v[3] = {0, 0, 0};
     for (int c = 0; c < C; ++c) {
@@ -316,7 +342,7 @@ __global__ void k_to_planes(ImageArg in, int32_t dtype, int32_t rgb_to_ycc, int3
                                 : static_cast<const float*>(in.data)[off + c * in.plane];
     }
     if (C == 3 && rgb_to_ycc) Ycc::from_rgb(v[0], v[1], v[2], v[0], v[1], v[2]);
-    for (int c = 0; c < C; ++c) out[c * o_plane + (int64_t)y * o_row + x] = v[c];
+    for (int c = 0; c < C; ++c) out[c * o_plane + (int64_t)yp * o_row + xp] = v[c];
 }
 
 __global__ void k_iota(int32_t* p, int64_t n) {
@@ -549,6 +575,9 @@ static int gram_tiles(const mdn_gram& g) {
     return T * (T + 1) / 2;
 }
 
+// elements of one padded gather plane of a w x h image
+static size_t padded_plane(int w, int h) { return (size_t)(w + 2 * kPad) * (size_t)(h + 2 * kPad); }
+
 size_t train_ws_bytes(const mdn_gram& g, int w, int h) {
     auto al = [](size_t v) { return (v + 255) / 256 * 256; };
     int D, nrhs, spk;
@@ -557,13 +586,14 @@ size_t train_ws_bytes(const mdn_gram& g, int w, int h) {
     const int wc = (w + 1) / 2, hc = (h + 1) / 2;
     const size_t n = (size_t)w * h;
     const size_t part = (size_t)g.K * spk * gram_segments((int64_t)n, g.K) * gram_tiles(g) * 1024 * 4;
-    return al(n * C * 4) * 2 + al((size_t)wc * hc * C * 4) + al(n * 2) * 2 + al(n * 4) * 2 +
+    return al(padded_plane(w, h) * C * 4) * 2 + al(padded_plane(wc, hc) * C * 4) + al(n * 2) * 2 + al(n * 4) * 2 +
            al(((size_t)g.K + 1) * 4) + al(sort_tmp_bytes((int64_t)n, g.K > 256)) + al(part);
 }
 
+// padded float32 gather planes of im (row pitch and plane pitch of the padded planes)
 mdn_status launch_to_planes(const mdn_image& im, float* out, int64_t row, int64_t plane, hipStream_t st) {
     ImageArg a{im.data, im.row_pitch, im.plane_pitch, im.width, im.height};
-    dim3 grid((im.width + 255) / 256, im.height);
+    dim3 grid((im.width + 2 * kPad + 255) / 256, im.height + 2 * kPad);
     k_to_planes<<<grid, 256, 0, st>>>(a, im.dtype, im.color == MDN_RGB, im.channels, out, row, plane);
     return check_launch("to_planes");
 }
@@ -575,13 +605,14 @@ mdn_status train_accumulate(const mdn_gram& g, const mdn_image& z, const mdn_ima
     const int W = z.width, H = z.height, C = z.channels;
     const int Wc = (W + 1) / 2, Hc = (H + 1) / 2;
     auto al = [](size_t v) { return (v + 255) / 256 * 256; };
+    const int Wp = W + 2 * kPad, Hp = H + 2 * kPad, Wcp = Wc + 2 * kPad, Hcp = Hc + 2 * kPad;
     char* p = static_cast<char*>(ws);
     float* fine = reinterpret_cast<float*>(p);
-    p += al((size_t)W * H * C * 4);
+    p += al(padded_plane(W, H) * C * 4);
     float* tgt = reinterpret_cast<float*>(p);
-    p += al((size_t)W * H * C * 4);
+    p += al(padded_plane(W, H) * C * 4);
     float* coarse = reinterpret_cast<float*>(p);
-    p += al((size_t)Wc * Hc * C * 4);
+    p += al(padded_plane(Wc, Hc) * C * 4);
     // selector map and sorted keys: uint8, or uint16 when K > 256
     const bool wide = g.K > 256;
     void* smap = p;
@@ -598,9 +629,9 @@ mdn_status train_accumulate(const mdn_gram& g, const mdn_image& z, const mdn_ima
     p += al(sort_tmp_bytes((int64_t)W * H, wide));
     float* part = reinterpret_cast<float*>(p);
     mdn_status s;
-    if ((s = launch_to_planes(z, fine, W, (int64_t)W * H, st))) return s;
-    if ((s = launch_to_planes(target, tgt, W, (int64_t)W * H, st))) return s;
-    if (uc && (s = launch_to_planes(*uc, coarse, Wc, (int64_t)Wc * Hc, st))) return s;
+    if ((s = launch_to_planes(z, fine, Wp, (int64_t)Wp * Hp, st))) return s;
+    if ((s = launch_to_planes(target, tgt, Wp, (int64_t)Wp * Hp, st))) return s;
+    if (uc && (s = launch_to_planes(*uc, coarse, Wcp, (int64_t)Wcp * Hcp, st))) return s;
     if ((s = launch_select_apply(z, uc, nullptr, W, smap, sel, nullptr, st))) return s;
     const int64_t npx = (int64_t)W * H;
     k_iota<<<256, 256, 0, st>>>(idx_in, npx);
@@ -621,10 +652,10 @@ mdn_status train_accumulate(const mdn_gram& g, const mdn_image& z, const mdn_ima
     a.planes = fine;
     a.target_off = (int32_t)(tgt - fine);
     a.coarse_off = (int32_t)(coarse - fine);
-    a.f_row = W;
-    a.f_plane = W * H;
-    a.c_row = Wc;
-    a.c_plane = Wc * Hc;
+    a.f_row = Wp;
+    a.f_plane = Wp * Hp;
+    a.c_row = Wcp;
+    a.c_plane = Wcp * Hcp;
     a.W = W;
     a.H = H;
     a.Wc = Wc;
@@ -634,20 +665,24 @@ mdn_status train_accumulate(const mdn_gram& g, const mdn_image& z, const mdn_ima
     a.D = D;
     a.nrhs = nrhs;
     a.per_channel = g.layout == MDN_X_PER_CHANNEL;
-    int f = 0;
+    // tap rows in feature order: x = [coarse taps, row-major; fine taps, row-major] and the
+    // target(s) last
+    int f = 0, nr = 0;
+    auto add_row = [&](int src, int plane, int dy, int r) {
+        a.rows[nr++] = row_pack(src, plane, dy, -r, 2 * r + 1, f);
+        f += 2 * r + 1;
+    };
     if (a.per_channel) {
         if (g.radius_f >= 1)
-            for (int dy = -g.radius_f; dy <= g.radius_f; ++dy)
-                for (int dx = -g.radius_f; dx <= g.radius_f; ++dx) a.feat[f++] = feat_pack(1, 0, dy, dx);
-        for (int dy = -g.radius_g; dy <= g.radius_g; ++dy)
-            for (int dx = -g.radius_g; dx <= g.radius_g; ++dx) a.feat[f++] = feat_pack(0, 0, dy, dx);
-        a.feat[f++] = feat_pack(2, 0, 0, 0);
+            for (int dy = -g.radius_f; dy <= g.radius_f; ++dy) add_row(1, 0, dy, g.radius_f);
+        for (int dy = -g.radius_g; dy <= g.radius_g; ++dy) add_row(0, 0, dy, g.radius_g);
+        add_row(2, 0, 0, 0);
     } else {
         for (int c = 0; c < C; ++c)
-            for (int dy = -g.radius_g; dy <= g.radius_g; ++dy)
-                for (int dx = -g.radius_g; dx <= g.radius_g; ++dx) a.feat[f++] = feat_pack(0, c, dy, dx);
-        for (int c = 0; c < C; ++c) a.feat[f++] = feat_pack(2, c, 0, 0);
+            for (int dy = -g.radius_g; dy <= g.radius_g; ++dy) add_row(0, c, dy, g.radius_g);
+        for (int c = 0; c < C; ++c) add_row(2, c, 0, 0);
     }
+    a.nrows = nr;
     a.Daug = f;
     a.nseg = gram_segments((int64_t)W * H, g.K);
     a.part = part;
@@ -658,10 +693,16 @@ mdn_status train_accumulate(const mdn_gram& g, const mdn_image& z, const mdn_ima
     const int T = (f + 31) / 32;
     dim3 grid(g.K, spk, a.nseg);
     bool launched = false;
-#define MDN_GRAM(P_, T_) \
-    if (!launched && precision == P_ && T == T_) { k_gram<P_, T_><<<grid, 256, 0, st>>>(a); launched = true; }
-    MDN_GRAM(0, 1) MDN_GRAM(0, 2) MDN_GRAM(0, 3) MDN_GRAM(0, 4) MDN_GRAM(0, 5)
-    MDN_GRAM(1, 1) MDN_GRAM(1, 2) MDN_GRAM(1, 3) MDN_GRAM(1, 4) MDN_GRAM(1, 5)
+    const int rpw = (nr + 3) / 4 <= 4 ? 4 : 6;
+#define MDN_GRAM(P_, T_, R_)                                                              \
+    if (!launched && precision == P_ && T == T_ && rpw == R_) {                            \
+        k_gram<P_, T_, R_><<<grid, 256, 0, st>>>(a);                                       \
+        launched = true;                                                                   \
+    }
+    MDN_GRAM(0, 1, 4) MDN_GRAM(0, 2, 4) MDN_GRAM(0, 3, 4) MDN_GRAM(0, 4, 4) MDN_GRAM(0, 5, 4)
+    MDN_GRAM(1, 1, 4) MDN_GRAM(1, 2, 4) MDN_GRAM(1, 3, 4) MDN_GRAM(1, 4, 4) MDN_GRAM(1, 5, 4)
+    MDN_GRAM(0, 2, 6) MDN_GRAM(0, 3, 6) MDN_GRAM(0, 4, 6) MDN_GRAM(0, 5, 6)
+    MDN_GRAM(1, 2, 6) MDN_GRAM(1, 3, 6) MDN_GRAM(1, 4, 6) MDN_GRAM(1, 5, 6)
 #undef MDN_GRAM
     if (!launched) return fail(MDN_ENOTSUP, "gram: %d features not supported", f);
     if ((s = check_launch("gram"))) return s;

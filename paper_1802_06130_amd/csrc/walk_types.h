@@ -101,12 +101,19 @@ struct BatchLaunch {
     D2Args d2[kMaxLevels];
     SelWalkArgs sel[kMaxLevels];
     WalkArgs walk[kMaxLevels];
+    // levels filtered by the tiled kernel (selection inline): one launch over the level's tile table
+    bool tiled[kMaxLevels];
+    mdn_level lv[kMaxLevels];
+    const TileImage* tiles[kMaxLevels];
+    int32_t n_imgs, n_tiles[kMaxLevels];
 };
 
 size_t batch_image_ws(int w, int h, int L, int storage);
 size_t batch_table_bytes(int n, int L);
+// tile: per-level descriptors for the tiled kernel, or null when not wanted
 void describe_cascade(const mdn_image& in, const mdn_image& out, void* ws, int L, int storage, const int (*rows)[3],
-                      int ncu, D2Image* d2, SelImage* sel, WalkImage* walk);
+                      int ncu, D2Image* d2, SelImage* sel, WalkImage* walk, TileImage* tile = nullptr);
+int tiles_of(const TileImage& t);
 int strips_of(const D2Image& d);
 int strips_of(const SelImage& d);
 int strips_of(const WalkImage& d);

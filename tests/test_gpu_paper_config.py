@@ -3,9 +3,10 @@ C ABI, against the oracle: 16 x 16 x 16 = 4096 buckets (uint16 selector maps), 7
 upscale filters, pyramid depth from the noise level.
 
 Bars as everywhere: bucket maps equal the oracle's except at pixels within 1e-6 of a bucket
-boundary; float32 cascades within 1e-4 of the oracle excluding pixels downstream of such a flip;
-the normal equations' sample counts exact and G within 2e-5 sqrt(G_pp G_qq). The batched and
-served forms keep the bank in LDS and refuse such banks with MDN_ENOTSUP.
+boundary; cascades within 1e-4 (float32) or 2e-3 (float16) of the oracle run on the GPU's maps,
+every pixel; the normal equations' sample counts exact and G within 2e-5 sqrt(G_pp G_qq). The
+batched form runs such banks on the tiled kernel in table mode and equals the per-image form bit
+for bit.
 """
 
 import numpy as np
@@ -35,10 +36,10 @@ def _host(t):
     return t.float().cpu().numpy().astype(np.float64)
 
 
-def _thresholds(zs):
+def _thresholds(zs, q=16):
     f = [O.level_features(z.astype(np.float64)) for z in zs]
-    return (O.thresholds_from_features(np.concatenate([x[0] for x in f]), 16),
-            O.thresholds_from_features(np.concatenate([x[1] for x in f]), 16))
+    return (O.thresholds_from_features(np.concatenate([x[0] for x in f]), q),
+            O.thresholds_from_features(np.concatenate([x[1] for x in f]), q))
 
 
 def _bank(L, rf, rg, seed=5):
@@ -161,9 +162,63 @@ def test_train_paper_configuration_end_to_end():
     assert err < 1e-3
 
 
-def test_batched_form_refuses_4096_buckets():
+@pytest.mark.parametrize("sigma,storage", [(25, "f16"), (5, "f16"), (25, "f32")])
+def test_batched_form_equals_plain_on_the_paper_configuration(sigma, storage):
+    """The batched form (one tiled launch per level over every image's 64 x 16 tiles, hipGraph
+    replay) on 4096-bucket banks with the sigma's footprints and depth equals mdn_denoise bit for
+    bit, on ragged images whose sizes cut tiles, strips and pyramid levels unevenly."""
     import paper_1802_06130_amd as M
     torch = _torch()
-    gb = gpu_bank(_bank(1, 2, 3), 3, coeff_dtype=torch.float16)
-    with pytest.raises(M.MdnError):
-        M.Plan(gb, M.F16, max_images=4)
+    L, rf, rg, _ = O.paper_setup(sigma)
+    f16 = storage == "f16"
+    print(f"batched paper configuration sigma={sigma} {storage}", flush=True)
+    gb = gpu_bank(_bank(L, rf, rg, seed=11), 3, coeff_dtype=torch.float16 if f16 else torch.float32)
+    code = M.F16 if f16 else M.F32
+    dt = np.float16 if f16 else np.float32
+    sizes = [(300, 412), (61, 97), (17, 129), (128, 40), (1, 1)]
+    zs = [_dev(synth.noisy_pair(2100 + i, h, w, 3, sigma, dtype=dt)[0]) for i, (h, w) in enumerate(sizes)]
+    plan = M.Plan(gb, code, max_images=8)
+    rows = plan.autotune(zs)
+    outs = None
+    for _ in range(2):                 # capture, then replay
+        outs = plan.denoise_batch(zs, outs, use_graph=True)
+    torch.cuda.synchronize()
+    for zt, ob, (h, w) in zip(zs, outs, sizes):
+        op = M.denoise(zt, gb, storage=code)
+        torch.cuda.synchronize()
+        assert torch.equal(ob, op), f"{h}x{w}: batched differs from per-image"
+    kt = plan.kernel_times(zs, reps=1)
+    print(f"  rows {rows}; kernel us per level {kt}", flush=True)
+    plan.close()
+
+
+def test_batched_form_equals_plain_on_a_phase_aware_bank():
+    import paper_1802_06130_amd as M
+    torch = _torch()
+    print("batched phase-aware bank", flush=True)
+    zs0 = [synth.noisy_pair(300 + i, 160, 160, 3, 25)[0].astype(np.float64) for i in range(3)]
+    levels = []
+    for lev in range(3):
+        t_s, t_c = _thresholds([O.build_pyramid(z, lev + 1)[lev] for z in zs0], 3)
+        co = synth.random_bank_coeffs(60 + lev, 24 * 3 * 3 * 4, 3, 49, 49)
+        levels.append(O.LevelBank(24, t_s, t_c, 3, 3, co, phases=4))
+    gb = gpu_bank(O.Bank(levels), 3, coeff_dtype=torch.float16)
+    zs = [_dev(synth.noisy_pair(2200 + i, h, w, 3, 25, dtype=np.float16)[0])
+          for i, (h, w) in enumerate([(250, 330), (61, 97), (33, 40)])]
+    plan = M.Plan(gb, M.F16, max_images=4)
+    outs = plan.denoise_batch(zs, use_graph=True)
+    torch.cuda.synchronize()
+    for zt, ob in zip(zs, outs):
+        assert torch.equal(ob, M.denoise(zt, gb, storage=M.F16))
+    plan.close()
+
+
+def test_plan_refusals():
+    """Single-scale banks and float32 banks that fit in LDS one channel at a time stay per-image."""
+    import paper_1802_06130_amd as M
+    torch = _torch()
+    from mdn_testlib import trained_bank_multiscale, trained_bank_single
+    for bank, dt in ((trained_bank_single(channels=3), torch.float32), (trained_bank_multiscale(levels=2), torch.float32)):
+        with pytest.raises(M.MdnError) as e:
+            M.Plan(gpu_bank(bank, 3, coeff_dtype=dt), M.F32, max_images=2)
+        assert e.value.status == M.MDN_ENOTSUP

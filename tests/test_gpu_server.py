@@ -104,3 +104,37 @@ def test_server_tick_granularity_and_staging(stages_per_tick, ahead):
     for i in range(len(zs)):
         assert np.array_equal(got[i], want[i]), f"request {i} {SIZES[i]} differs"
     srv.close()
+
+
+def test_server_mixes_column_walk_and_tiled_banks():
+    """A bank of the paper's own configuration (16 x 16 x 16 buckets, 7x7 denoise / 5x5 upscale
+    filters, the tiled kernel with inline selection) served beside a column-walk bank: every request
+    equals the plain per-image denoiser bit for bit, alone and in the mix."""
+    import torch
+    import paper_1802_06130_amd as M
+    import oracle as O
+    walk_bank = _banks(M, torch)[0]
+    zs0 = [synth.noisy_pair(300 + i, 160, 160, 3, 25)[0].astype(np.float64) for i in range(3)]
+    lvs = []
+    for lev in range(3):
+        f = [O.level_features(O.build_pyramid(z, lev + 1)[lev]) for z in zs0]
+        t_s = O.thresholds_from_features(np.concatenate([x[0] for x in f]), 16)
+        t_c = O.thresholds_from_features(np.concatenate([x[1] for x in f]), 16)
+        co = synth.random_bank_coeffs(80 + lev, 4096, 3, 25, 49)
+        lvs.append(M.Level(16, t_s, t_c, 3, 2, torch.from_numpy(co).to(torch.float16).cuda(), 3))
+    tiled_bank = M.Bank(lvs)
+    banks = [walk_bank, tiled_bank]
+    zs = _inputs(torch, np.float16)
+    which = [i % 2 for i in range(len(zs))]
+    want = _plain(M, banks, zs, which, M.F16)
+    srv = M.Server(banks, storage=M.F16, max_slots=4, hbm_budget=1 << 30)
+    alone = _alone(M, srv, zs, which)
+    for i, (a, w) in enumerate(zip(alone, want)):
+        assert np.array_equal(a, w), f"request {i} {SIZES[i]} bank {which[i]} alone differs"
+    outs = [z.new_empty(z.shape).pin_memory() for z in zs]
+    reqs = [M.Server.request(z, b, o) for z, b, o in zip(zs, which, outs)]
+    done = srv.replay(reqs, synth.poisson_arrivals(5000.0, len(zs), 5300))
+    assert all(c["status"] == M.MDN_OK for c in done), done
+    for i, (o, w) in enumerate(zip(outs, want)):
+        assert np.array_equal(o.numpy(), w), f"request {i} {SIZES[i]} bank {which[i]} differs in the mix"
+    srv.close()

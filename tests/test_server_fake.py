@@ -247,8 +247,8 @@ def test_bad_configurations():
     with pytest.raises(M.MdnError) as e:
         _server(banks=[M.Bank([lv])])
     assert e.value.status == M.MDN_ENOTSUP
-    # banks built around the column walks only: levels that select on the coarser output, and
-    # phase-aware levels, are refused
+    # float16 7x7/7x7 levels that select on the coarser output, and banks that run the LDS-bank kernel
+    # per image (this phase-aware bank of 216 buckets), are refused
     co = torch.zeros(216, 3, 98, dtype=torch.float16)
     for lvx in (M.Level(24, [0.01, 0.02], [0.3, 0.6], 3, 3, co, 3, M.SELECT_COARSE),
                 M.Level(6, [0.01, 0.02], [0.3, 0.6], 3, 3, co, 3, M.SELECT_RGB, 4)):
@@ -265,6 +265,19 @@ def test_bad_configurations():
     with pytest.raises(M.MdnError) as e:
         srv.submit_request(_req(64, 64, dtype=M.F16))
     assert e.value.status == M.MDN_ENOTSUP
+
+
+def test_tiled_bank_levels_take_one_launch_each():
+    """Levels of the tiled kernel (the paper's 16 x 16 x 16 buckets, 7x7 / 5x5 filters) select inline:
+    a request alone takes L pyramid launches and L filtering launches, no selection launch."""
+    lv = M.Level(16, list(np.linspace(0.01, 0.2, 15)), list(np.linspace(0.05, 0.9, 15)), 3, 2,
+                 torch.zeros(4096, 3, 74, dtype=torch.float16), 3)
+    srv = _server(banks=[M.Bank([lv] * LEVELS)])
+    srv.submit_request(_req(640, 480))
+    (c,) = _run(srv)
+    assert c["status"] == M.MDN_OK
+    assert srv.stats()["launches"] == 2 * LEVELS
+    srv.close()
 
 
 SIZES = [(1280, 720), (1920, 1080), (4032, 3024)]
