@@ -28,6 +28,9 @@ The roofline object reports the dominant kernel, the batched form's level-0 filt
 against the HBM roofline (algorithmic bytes per launch / its HIP-event duration), with the unit that
 actually limits it (the LDS coefficient gathers) and the dot2 issue rate beside it.
 
+Beside them: the single-level grey method of Eq. (1) on 256x256 (latency), and the 3-level float32
+RGB cascade on 1024x768 (MP/s and its HBM roofline at 52.5 algorithmic bytes per pixel).
+
 The paper's own configuration at sigma 25 (16 x 16 x 16 buckets, 7x7 / 5x5 filters, 5 levels,
 float16) runs the same batch in the batched form beside it (paper_config_batched).
 
@@ -350,7 +353,21 @@ def run_training(M, torch, pairs):
         co, nfb = M.train_solve(g, 1e-3)
         res[name] = {"G": g.G.cpu().numpy().reshape(K, C, D, D), "n": g.n.cpu().numpy(),
                      "h": co.double().cpu().numpy(), "fallback": nfb}
-    sample = {"pairs": sub, "results": res, "t_s": np.asarray(t_s), "t_c": np.asarray(t_c), "K": K, "C": C, "D": D}
+    # cross-channel layout (x = the 7x7 taps of all three channels, D = 147, one Gram per bucket and
+    # three right-hand sides), single scale on the same pairs and thresholds
+    selx = M.Level(Q_THETA, t_s, t_c, RADIUS, None, torch.zeros((K, C, 49), device=dev), 3)
+    resx = {}
+    for name, prec in (("fp32_mfma", M.GRAM_F32), ("bf16x3_mfma", M.GRAM_BF16X3)):
+        g = M.Gram(K, C, RADIUS, None, layout=M.X_CROSS_CHANNEL, device=dev)
+        for z, u, _ in list(zip(zs, us, coarse))[:ACC_TRAIN_PAIRS]:
+            M.train_accumulate(g, z, u, selx, precision=prec)
+        co, nfb = M.train_solve(g, 1e-3)
+        resx[name] = {"G": g.G.cpu().numpy().reshape(K, 147, 147), "n": g.n.cpu().numpy(),
+                      "h": co.double().cpu().numpy(), "fallback": nfb}
+    for p, (z, _, _) in zip(sub, list(zip(zs, us, coarse))[:ACC_TRAIN_PAIRS]):
+        p["s0"] = M.select_filters(z, selx).cpu().numpy()
+    sample = {"pairs": sub, "results": res, "results_cross": resx, "t_s": np.asarray(t_s), "t_c": np.asarray(t_c),
+              "K": K, "C": C, "D": D}
     return out, sample
 
 
@@ -388,6 +405,67 @@ def run_paper_config_batched(M, torch, zs, steps, warmup, sigma=25):
             "kernel_us_per_level": [[round(t, 1) for t in lv] for lv in kt],
             "what": "paper configuration at sigma 25 (16x16x16 buckets, 7x7 g / 5x5 f, 5 levels), float16, "
                     "batched form on the same 64 images: tiled select-and-filter kernel, one launch per level"}
+
+
+def _time_calls(torch, fn, reps=50, warmup=5):
+    """Device time of each of `reps` calls (HIP events on the current stream), in microseconds."""
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in evs:
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    return np.array([a.elapsed_time(b) * 1e3 for a, b in evs])
+
+
+def run_single_level_grey(M, torch):
+    """Single-level plain method (Eq. (1)) on a grey 256x256 float32 image: 16 x 3 x 3 buckets of 5x5
+    filters trained on the GPU from 8 seeded 128x128 pairs at sigma 25; one mdn_denoise call per
+    image, latency-bound at this size. Algorithmic HBM bytes: read 4 + write 4 per pixel."""
+    dev = torch.device("cuda:0")
+    pairs = [synth.noisy_pair(1 + i, 128, 128, 1, SIGMA) for i in range(8)]
+    pairs = [(torch.from_numpy(z).to(dev), torch.from_numpy(u).to(dev)) for z, u in pairs]
+    bank, _, _ = M.train_single(pairs, 16, 3, 3, 2, 1e-3)
+    z, u = synth.noisy_pair(1001, 256, 256, 1, SIGMA)
+    zt = torch.from_numpy(z).to(dev)
+    out = torch.empty_like(zt)
+    us = _time_calls(torch, lambda: M.denoise(zt, bank, M.F32, out=out))
+    med = float(np.median(us))
+    return {"latency_us": {"p50": round(med, 2), "p99": round(float(np.percentile(us, 99)), 2)},
+            "MP_s": round(256 * 256 / med, 1), "hbm_GB_s": round(8.0 * 256 * 256 / med * 1e-3, 1),
+            "what": "grey 256x256 float32, 16x3x3 buckets, 5x5 filters (Eq. (1)), one mdn_denoise call; "
+                    "latency-bound (65k pixels)"}, (z, u, bank, out.cpu().numpy())
+
+
+def run_three_level_f32(M, torch):
+    """3-level RGB 1024x768 float32 cascade, 7x7 upscale and denoise filters, 24 x 3 x 3 buckets,
+    trained on the GPU from 64 seeded 256x256 pairs with sigma drawn from {15, 25, 50}/255 (rng(2));
+    one seeded test image at sigma 25. Algorithmic HBM bytes 52.5 per pixel in float32."""
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(2)
+    sig = rng.choice([15.0, 25.0, 50.0], 64)
+    pairs = [synth.noisy_pair(1 + i, 256, 256, 3, float(g)) for i, g in enumerate(sig)]
+    pairs = [(torch.from_numpy(z).to(dev), torch.from_numpy(u).to(dev)) for z, u in pairs]
+    bank, _, _ = M.train_multiscale(pairs, 2, Q_THETA, Q_S, Q_C, RADIUS, RADIUS, 1e-3)
+    z, u = synth.noisy_pair(2001, 768, 1024, 3, SIGMA)
+    zt = torch.from_numpy(z).to(dev)
+    out = torch.empty_like(zt)
+    ws = torch.empty(M.denoise_workspace_size(1024, 768, 3, 2, M.F32), dtype=torch.uint8, device=dev)
+    us = _time_calls(torch, lambda: M.denoise(zt, bank, M.F32, ws=ws, out=out))
+    med = float(np.median(us))
+    px = 1024 * 768
+    hbm = 52.5 * px / med * 1e-3
+    pyr = [zt] + M.pyramid_build(zt, 2, storage=torch.float32)
+    maps = [M.select_filters(pyr[l], bank.levels[l]).cpu().numpy().astype(np.int64) for l in range(2)]
+    return {"MP_s": round(px / med, 1), "latency_us": {"p50": round(med, 2), "p99": round(float(np.percentile(us, 99)), 2)},
+            "roofline": {"bound": "hbm", "achieved": round(hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(hbm / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_px": 52.5},
+            "what": "RGB 1024x768 float32, 3 levels, 7x7/7x7, 24x3x3 buckets, one mdn_denoise call (selection "
+                    "pass + LDS-bank filtering per level)"}, (z, u, bank, out.cpu().numpy(), maps)
 
 
 def time_level0_filter(M, torch, zs, bank, n=16, reps=3):
@@ -530,7 +608,8 @@ def gpu_crop_outputs(M, torch, crops, bank16):
     return res
 
 
-def cpu_baseline_leg(crops, clean_crops, gpu_crops, bank16_dev, bank32_dev, train_sample, budget_s=20.0):
+def cpu_baseline_leg(crops, clean_crops, gpu_crops, bank16_dev, bank32_dev, train_sample, c1=None, c2=None,
+                     budget_s=20.0):
     """The FP64 oracle on a bounded sample of the same workload (the leading crops), timed; then the
     accuracy of the GPU results on that sample against it:
     * inference (the crops through the batched form): bucket flips per level against the oracle's
@@ -607,7 +686,39 @@ def cpu_baseline_leg(crops, clean_crops, gpu_crops, bank16_dev, bank32_dev, trai
                         "gram_worst_rel": float(f"{np.max(np.abs(r['G'] - st.G) / (d[..., :, None] * d[..., None, :] + 1e-300)):.3g}"),
                         "coeff_max_abs": float(f"{np.max(np.abs(dh)):.3g}"),
                         "output_space_rel": float(f"{np.sqrt(max(e, 0.0) / st.yy.sum()):.3g}")}
+        stx = O.CrossGramStats.zeros(K, C, 147)
+        for p in ts["pairs"]:
+            O.accumulate_level_cross(stx, p["s0"].astype(np.int64), O.to_filter_space(np.asarray(p["z"], np.float64)),
+                                     O.to_filter_space(np.asarray(p["u"], np.float64)), RADIUS)
+        hx, _ = O.solve_level_cross(stx, 1e-3)
+        dx = np.sqrt(np.maximum(np.einsum("kii->ki", stx.G), 0.0))
+        trx = {"layout": "cross-channel, D = 147 (single scale, level 0)"}
+        for name, r in ts["results_cross"].items():
+            dh = r["h"] - hx
+            e = np.einsum("kcd,kde,kce->", dh, stx.G, dh)
+            trx[name] = {"counts_equal": bool(np.array_equal(r["n"], stx.n)),
+                         "gram_worst_rel": float(f"{np.max(np.abs(r['G'] - stx.G) / (dx[:, :, None] * dx[:, None, :] + 1e-300)):.3g}"),
+                         "coeff_max_abs": float(f"{np.max(np.abs(dh)):.3g}"),
+                         "output_space_rel": float(f"{np.sqrt(max(e, 0.0) / stx.yy.sum()):.3g}")}
+        tr["cross_D147"] = trx
         acc["training"] = tr
+    if c1 is not None:
+        z, u, bank_dev, got = c1
+        lb = bank_dev.levels[0]
+        b1 = O.Bank([O.LevelBank(lb.q_theta, lb.t_s, lb.t_c, lb.radius_g, None, lb.coeffs.double().cpu().numpy())])
+        ref = O.denoise(np.asarray(z, np.float64), b1, storage=np.float32)
+        acc["single_level_grey"] = {"max_abs_vs_fp64_fp32_mode": float(f"{np.max(np.abs(got - ref)):.3g}"),
+                                    "psnr_noisy_db": round(O.psnr(np.asarray(z, np.float64), u), 3),
+                                    "psnr_gpu_db": round(O.psnr(np.asarray(got, np.float64), u), 3)}
+    if c2 is not None:
+        z, u, bank_dev, got, maps = c2
+        b2 = host_bank(bank_dev)
+        at = O.denoise(np.asarray(z, np.float64), b2, storage=np.float32, maps=maps)
+        ref64 = O.denoise(np.asarray(z, np.float64), b2)
+        acc["three_level_f32"] = {"max_abs_vs_fp32_mode_at_gpu_maps": float(f"{np.max(np.abs(got - at)):.3g}"),
+                                  "max_abs_vs_fp64": float(f"{np.max(np.abs(got - ref64)):.3g}"),
+                                  "psnr_noisy_db": round(O.psnr(np.asarray(z, np.float64), u), 3),
+                                  "psnr_gpu_db": round(O.psnr(np.asarray(got, np.float64), u), 3)}
     return base, acc
 
 
@@ -752,6 +863,10 @@ def main():
     }
     if f32 is not None:
         line["plain_f32"] = f32
+    line["single_level_grey"], c1 = run_single_level_grey(M, torch)
+    line["three_level_f32"], c2 = run_three_level_f32(M, torch)
+    print(f"# single level grey: {line['single_level_grey']}\n# three level f32: {line['three_level_f32']}",
+          file=sys.stderr, flush=True)
     if not args.no_paper_config:
         line["paper_config_batched"] = run_paper_config_batched(M, torch, zs, max(2, args.steps // 2), 1)
         print(f"# paper configuration batched: {line['paper_config_batched']}", file=sys.stderr, flush=True)
@@ -771,7 +886,7 @@ def main():
         line["served"] = run_served(M, torch, banks, (50, 200, 800), args.serve_requests, serve_imgs)
     if not args.no_cpu_baseline:
         line["cpu_baseline"], line["accuracy"] = cpu_baseline_leg(crops, clean_crops, gpu_crops, bank16, bank32,
-                                                                  train_sample)
+                                                                  train_sample, c1, c2)
     print(json.dumps(line), flush=True)
 
 
