@@ -290,28 +290,39 @@ typedef struct mdn_plan mdn_plan;
  * creates its own stream, and allocates its device workspace and tables on first use: creation
  * and the first batch of a new size are the only calls that allocate. storage: pyramid dtype. */
 mdn_status mdn_plan_create(const mdn_bank* bank, int32_t storage, int32_t max_images, mdn_plan** plan);
+/* A plan over n_banks (1..8) banks, each accepted as by mdn_plan_create; they may differ in depth
+ * (the paper's configuration deepens the pyramid with the noise level, Section 5). Every image of a
+ * batch names its bank; the pyramid steps run over all images deep enough, and each level's
+ * selection and filtering run one launch per bank over that bank's images. */
+mdn_status mdn_plan_create_banks(const mdn_bank* banks, int32_t n_banks, int32_t storage, int32_t max_images,
+                                 mdn_plan** plan);
 mdn_status mdn_plan_destroy(mdn_plan* plan);
 
+/* The batch calls below take, beside in[] and out[], bank: host int32[n], bank[i] the index of
+ * image i's bank in the plan (0..n_banks-1), or NULL for bank 0 throughout. */
+
 /* Time candidate strip heights of every kernel and level on this batch and keep the fastest
- * (rows_out, optional host int32[3*levels]: pyramid, selection, filtering rows per level). Runs
- * the batch once; ordered after prior work on `stream` and before later work. */
-mdn_status mdn_plan_autotune(mdn_plan* plan, const mdn_image* in, const mdn_image* out, int32_t n,
-                             int32_t* rows_out, void* stream);
+ * (rows_out, optional host int32[3*levels], levels = the deepest bank's: pyramid, selection,
+ * filtering rows per level, shared by the banks). Runs the batch once; ordered after prior work
+ * on `stream` and before later work. */
+mdn_status mdn_plan_autotune(mdn_plan* plan, const mdn_image* in, const mdn_image* out, const int32_t* bank,
+                             int32_t n, int32_t* rows_out, void* stream);
 
 /* Device time of every launch of this batch: the launches of mdn_denoise_batch, in the same order
- * and with the same strip heights but without a graph, each started on the idle plan stream between
- * two HIP events, `reps` times (1..1000); us_out (host float[3*levels]) receives the mean microseconds per
- * launch of the pyramid, selection and filtering kernels of each level (index 3 l + k; a level on the
- * tiled kernel reports its one launch as filtering and about nothing for selection). The outputs
- * are written as by mdn_denoise_batch. Synchronises the plan's stream. */
-mdn_status mdn_plan_kernel_times(mdn_plan* plan, const mdn_image* in, const mdn_image* out, int32_t n,
-                                 int32_t reps, float* us_out, void* stream);
+ * and with the same strip heights but without a graph, each kind of each level started on the idle
+ * plan stream between two HIP events, `reps` times (1..1000); us_out (host float[3*levels]) receives
+ * the mean microseconds of the pyramid, selection and filtering launches of each level (index
+ * 3 l + k, all banks together; a level on the tiled kernel reports its launches as filtering and
+ * about nothing for selection). The outputs are written as by mdn_denoise_batch. Synchronises the
+ * plan's stream. */
+mdn_status mdn_plan_kernel_times(mdn_plan* plan, const mdn_image* in, const mdn_image* out, const int32_t* bank,
+                                 int32_t n, int32_t reps, float* us_out, void* stream);
 
-/* Denoise n images (in[i] -> out[i], RGB, equal sizes per pair, one dtype per side). With
- * use_graph != 0 the launches are captured once per batch (same images, sizes and buffers) and
- * replayed afterwards. Ordered after prior work on `stream` and before later work. */
-mdn_status mdn_denoise_batch(mdn_plan* plan, const mdn_image* in, const mdn_image* out, int32_t n,
-                             int32_t use_graph, void* stream);
+/* Denoise n images (in[i] -> out[i] with bank[i], RGB, equal sizes per pair, one dtype per side).
+ * With use_graph != 0 the launches are captured once per batch (same images, sizes, banks and
+ * buffers) and replayed afterwards. Ordered after prior work on `stream` and before later work. */
+mdn_status mdn_denoise_batch(mdn_plan* plan, const mdn_image* in, const mdn_image* out, const int32_t* bank,
+                             int32_t n, int32_t use_graph, void* stream);
 
 /* ---------------------------------------------------------------------------------------
  * Serving loop (host code above the calls of this header): requests of any sizes arrive over

@@ -518,10 +518,11 @@ def _plan_sigs(L):
     P = ct.POINTER
     sig = {
         "mdn_plan_create": [P(MdnBank), i32, i32, P(vp)],
+        "mdn_plan_create_banks": [P(MdnBank), i32, i32, i32, P(vp)],
         "mdn_plan_destroy": [vp],
-        "mdn_plan_autotune": [vp, P(MdnImage), P(MdnImage), i32, P(i32), vp],
-        "mdn_denoise_batch": [vp, P(MdnImage), P(MdnImage), i32, i32, vp],
-        "mdn_plan_kernel_times": [vp, P(MdnImage), P(MdnImage), i32, i32, P(ct.c_float), vp],
+        "mdn_plan_autotune": [vp, P(MdnImage), P(MdnImage), P(i32), i32, P(i32), vp],
+        "mdn_denoise_batch": [vp, P(MdnImage), P(MdnImage), P(i32), i32, i32, vp],
+        "mdn_plan_kernel_times": [vp, P(MdnImage), P(MdnImage), P(i32), i32, i32, P(ct.c_float), vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -530,43 +531,52 @@ def _plan_sigs(L):
 
 
 class Plan:
-    """Batched denoiser: one persistent launch per kernel and level over a list of images."""
+    """Batched denoiser: one persistent launch per kernel, level and bank over a list of images.
+    ``bank`` is one Bank or a list of them; the batch calls then take ``banks``, one index per
+    image (None: bank 0 throughout)."""
 
-    def __init__(self, bank: Bank, storage: int = F16, max_images: int = 256):
+    def __init__(self, bank, storage: int = F16, max_images: int = 256):
         _plan_sigs(lib())
-        self.bank = bank                       # keeps the coefficient tensors alive
-        self.levels = len(bank.levels)
+        banks = list(bank) if isinstance(bank, (list, tuple)) else [bank]
+        self.banks = banks                     # keeps the coefficient tensors alive
+        self.levels = max(len(b.levels) for b in banks)
         h = ct.c_void_p()
-        _check(lib().mdn_plan_create(ct.byref(bank.desc()), storage, max_images, ct.byref(h)))
+        if len(banks) == 1:
+            _check(lib().mdn_plan_create(ct.byref(banks[0].desc()), storage, max_images, ct.byref(h)))
+        else:
+            self._descs_b = [b.desc() for b in banks]
+            arr = (MdnBank * len(banks))(*self._descs_b)
+            _check(lib().mdn_plan_create_banks(arr, len(banks), storage, max_images, ct.byref(h)))
         self.handle = h
 
-    def _descs(self, ins, outs):
+    def _descs(self, ins, outs, banks):
         n = len(ins)
         a = (MdnImage * n)(*[image(t, RGB) for t in ins])
         b = (MdnImage * n)(*[image(t, RGB) for t in outs])
-        return n, a, b
+        k = None if banks is None else (ct.c_int32 * n)(*[int(x) for x in banks])
+        return n, a, b, k
 
-    def autotune(self, ins, outs=None):
+    def autotune(self, ins, outs=None, banks=None):
         outs = outs if outs is not None else [_torch().empty_like(t) for t in ins]
-        n, a, b = self._descs(ins, outs)
+        n, a, b, k = self._descs(ins, outs, banks)
         rows = (ct.c_int32 * (3 * self.levels))()
-        _check(lib().mdn_plan_autotune(self.handle, a, b, n, rows, _stream_ptr()))
+        _check(lib().mdn_plan_autotune(self.handle, a, b, k, n, rows, _stream_ptr()))
         return [tuple(rows[3 * l:3 * l + 3]) for l in range(self.levels)]
 
-    def kernel_times(self, ins, outs=None, reps: int = 3):
+    def kernel_times(self, ins, outs=None, reps: int = 3, banks=None):
         """Mean device microseconds per launch of the batch's kernels: a list over levels of
         (pyramid, selection, filtering), from HIP events on the plan's stream (synchronises)."""
         outs = outs if outs is not None else [_torch().empty_like(t) for t in ins]
-        n, a, b = self._descs(ins, outs)
+        n, a, b, k = self._descs(ins, outs, banks)
         us = (ct.c_float * (3 * self.levels))()
-        _check(lib().mdn_plan_kernel_times(self.handle, a, b, n, int(reps), us, _stream_ptr()))
+        _check(lib().mdn_plan_kernel_times(self.handle, a, b, k, n, int(reps), us, _stream_ptr()))
         return [tuple(float(x) for x in us[3 * l:3 * l + 3]) for l in range(self.levels)]
 
-    def denoise_batch(self, ins, outs=None, use_graph: bool = True):
+    def denoise_batch(self, ins, outs=None, use_graph: bool = True, banks=None):
         outs = outs if outs is not None else [_torch().empty_like(t) for t in ins]
-        n, a, b = self._descs(ins, outs)
-        self._keep = (a, b)
-        _check(lib().mdn_denoise_batch(self.handle, a, b, n, 1 if use_graph else 0, _stream_ptr()))
+        n, a, b, k = self._descs(ins, outs, banks)
+        self._keep = (a, b, k)
+        _check(lib().mdn_denoise_batch(self.handle, a, b, k, n, 1 if use_graph else 0, _stream_ptr()))
         return outs
 
     def close(self):

@@ -1,9 +1,10 @@
-// Batched form of the cascade: a list of images of any sizes is denoised level by level with one
-// persistent launch per kernel and level over all images (pyramid levels, selection pass,
-// filtering pass), from device-resident image tables. A plan owns the per-image pyramids, the
-// tables and an internal stream; with graphs enabled the launches of a batch are captured once
-// and replayed while the same batch (same images, sizes and buffers) comes back. The strip height
-// of every kernel and level comes from the plan's autotuner (timed candidates) or a default.
+// Batched form of the cascade: a list of images of any sizes, each with one of the plan's banks, is
+// denoised level by level with one persistent launch per kernel, level and bank over all the images
+// concerned (pyramid levels over every image deep enough; selection and filtering over the images
+// of one bank), from device-resident image tables. A plan owns the per-image pyramids, the tables
+// and an internal stream; with graphs enabled the launches of a batch are captured once and
+// replayed while the same batch (same images, sizes, banks and buffers) comes back. The strip
+// height of every kernel and level comes from the plan's autotuner (timed candidates) or a default.
 
 #include <stdio.h>
 #include <string.h>
@@ -48,13 +49,19 @@ size_t image_ws(int w, int h, int L, int storage) {
 
 }  // namespace
 
-struct mdn_plan {
-    int device = 0;
-    int storage = MDN_F16;
+struct PlanBank {
     int L = 0;
     mdn_level lv[kMaxLevels];
     double thr[kMaxLevels][2][kMaxThr];
     SelWalkArgs selc[kMaxLevels];
+};
+
+struct mdn_plan {
+    int device = 0;
+    int storage = MDN_F16;
+    int n_banks = 0;
+    int Lmax = 0;
+    PlanBank bank[kMaxPlanBanks];
     int max_images = 0;
     char* ws = nullptr;
     size_t ws_cap = 0;
@@ -74,11 +81,12 @@ struct mdn_plan {
 
 namespace {
 
-std::vector<uint64_t> signature(const mdn_image* in, const mdn_image* out, int n) {
+std::vector<uint64_t> signature(const mdn_image* in, const mdn_image* out, const int32_t* bank, int n) {
     std::vector<uint64_t> s;
-    s.reserve(n * 8 + 1);
+    s.reserve(n * 9 + 1);
     s.push_back((uint64_t)n);
     for (int i = 0; i < n; ++i) {
+        s.push_back(bank ? (uint64_t)(uint32_t)bank[i] : 0);
         // every field that the tables or the captured launches depend on, each in a word of its own
         s.push_back((uint64_t)in[i].data);
         s.push_back((uint64_t)out[i].data);
@@ -127,11 +135,6 @@ mdn_status ensure_tables(mdn_plan* p, size_t need) {
 namespace mdn {
 
 size_t batch_image_ws(int w, int h, int L, int storage) { return image_ws(w, h, L, storage) + al256((size_t)w * h); }
-
-size_t batch_table_bytes(int n, int L) {
-    return al256(sizeof(D2Image) * n) * L + al256(sizeof(SelImage) * n) * L + al256(sizeof(WalkImage) * n) * L +
-           al256(sizeof(TileImage) * n) * L;
-}
 
 // Per-level descriptors of one image's cascade, each with strip_begin = 0: d2[l] makes z^{l+1}
 // from z^l, sel[l] and walk[l] run level l (walk[0] writes `out`). ws (batch_image_ws bytes,
@@ -220,158 +223,210 @@ int strips_of(const D2Image& d) { return d.nsx * ((d.Ho + d.rows - 1) / d.rows);
 int strips_of(const SelImage& d) { return d.nsx * ((d.H + d.rows - 1) / d.rows); }
 int strips_of(const WalkImage& d) { return d.nsx * ((d.H + d.rows - 1) / d.rows); }
 
-// Launch tables of one batch: image i uses the workspace ws[i] (batch_image_ws bytes, 256-aligned).
-// Tables go to tab_host (pinned) and are meant to be copied to tab_dev before the launches.
-// rows: per level {pyramid, selection, filtering} strip heights, or null for the defaults.
-mdn_status build_batch(const mdn_level* lv, const SelWalkArgs* selc, int L, int storage, const mdn_image* in,
-                       const mdn_image* out, void* const* ws, int n, const int (*rows)[3], char* tab_host,
-                       char* tab_dev, BatchLaunch* bl) {
-    const int ncu = device_cus();
-    std::vector<D2Image> d2((size_t)n * L);
-    std::vector<SelImage> sel((size_t)n * L);
-    std::vector<WalkImage> walk((size_t)n * L);
-    std::vector<TileImage> tile((size_t)n * L);
-    for (int i = 0; i < n; ++i)
-        describe_cascade(in[i], out[i], ws[i], L, storage, rows, ncu, &d2[(size_t)i * L], &sel[(size_t)i * L],
-                         &walk[(size_t)i * L], &tile[(size_t)i * L]);
-    char* th = tab_host;
-    char* td = tab_dev;
-    for (int l = 0; l < L; ++l) {
-        D2Image* t = reinterpret_cast<D2Image*>(th);
-        int begin = 0;
-        for (int i = 0; i < n; ++i) {
-            t[i] = d2[(size_t)i * L + l];
-            t[i].strip_begin = begin;
-            begin += strips_of(t[i]);
-        }
-        memset(&bl->d2[l], 0, sizeof(D2Args));
-        bl->d2[l].imgs = reinterpret_cast<const D2Image*>(td);
-        bl->d2[l].n_imgs = n;
-        bl->d2[l].n_strips = begin;
-        th += al256(sizeof(D2Image) * n);
-        td += al256(sizeof(D2Image) * n);
-    }
-    for (int l = 0; l < L; ++l) {
-        SelImage* t = reinterpret_cast<SelImage*>(th);
-        int begin = 0;
-        for (int i = 0; i < n; ++i) {
-            t[i] = sel[(size_t)i * L + l];
-            t[i].strip_begin = begin;
-            begin += strips_of(t[i]);
-        }
-        bl->sel[l] = selc[l];
-        bl->sel[l].imgs = reinterpret_cast<const SelImage*>(td);
-        bl->sel[l].n_imgs = n;
-        bl->sel[l].n_strips = begin;
-        th += al256(sizeof(SelImage) * n);
-        td += al256(sizeof(SelImage) * n);
-    }
-    for (int l = 0; l < L; ++l) {
-        WalkImage* t = reinterpret_cast<WalkImage*>(th);
-        int begin = 0;
-        for (int i = 0; i < n; ++i) {
-            t[i] = walk[(size_t)i * L + l];
-            t[i].strip_begin = begin;
-            begin += strips_of(t[i]);
-        }
-        memset(&bl->walk[l], 0, sizeof(WalkArgs));
-        bl->walk[l].imgs = reinterpret_cast<const WalkImage*>(td);
-        bl->walk[l].n_imgs = n;
-        bl->walk[l].n_strips = begin;
-        bl->walk[l].coeffs = lv[l].coeffs;
-        bl->walk[l].coeff_dtype = lv[l].coeff_dtype;
-        bl->walk[l].K = level_buckets(lv[l]);
-        th += al256(sizeof(WalkImage) * n);
-        td += al256(sizeof(WalkImage) * n);
-    }
-    for (int l = 0; l < L; ++l) {
-        TileImage* t = reinterpret_cast<TileImage*>(th);
-        int begin = 0;
-        for (int i = 0; i < n; ++i) {
-            t[i] = tile[(size_t)i * L + l];
-            t[i].tile_begin = begin;
-            begin += tiles_of(t[i]);
-        }
-        bl->tiled[l] = level_runs_tiled(lv[l], 3);
-        bl->lv[l] = lv[l];
-        bl->tiles[l] = reinterpret_cast<const TileImage*>(td);
-        bl->n_tiles[l] = begin;
-        th += al256(sizeof(TileImage) * n);
-        td += al256(sizeof(TileImage) * n);
-    }
-    bl->n_imgs = n;
-    bl->L = L;
-    bl->storage = storage;
-    bl->in_dtype = in[0].dtype;
-    bl->out_dtype = out[0].dtype;
-    bl->table_bytes = (size_t)(th - tab_host);
-    return MDN_OK;
-}
-
-mdn_status launch_batch_level_d2(const BatchLaunch& b, int l, hipStream_t st) {
-    return launch_down2_args(b.d2[l], 3, l == 0 ? b.in_dtype : b.storage, b.storage, st);
-}
-mdn_status launch_batch_level_sel(const BatchLaunch& b, int l, hipStream_t st) {
-    if (b.tiled[l]) return MDN_OK;                         // selection runs inside the tiled kernel
-    return launch_select_args(b.sel[l], 3, l == 0 ? b.in_dtype : b.storage, st);
-}
-mdn_status launch_batch_level_walk(const BatchLaunch& b, int l, hipStream_t st) {
-    if (b.tiled[l])
-        return launch_select_apply_table(b.lv[l], b.tiles[l], b.n_imgs, b.n_tiles[l], 3, l == 0 ? b.in_dtype : b.storage,
-                                         b.storage, l == b.L - 1 ? MDN_RGB : MDN_YCC, l == 0 ? b.out_dtype : b.storage,
-                                         l == 0 ? MDN_RGB : MDN_YCC, st);
-    return launch_walk_args(b.walk[l], l == 0 ? b.in_dtype : b.storage, b.storage, l == 0 ? b.out_dtype : b.storage, st);
-}
-
-mdn_status launch_batch(const BatchLaunch& b, hipStream_t st) {
-    mdn_status e;
-    for (int l = 0; l < b.L; ++l)
-        if ((e = launch_batch_level_d2(b, l, st))) return e;
-    for (int l = b.L - 1; l >= 0; --l) {
-        if ((e = launch_batch_level_sel(b, l, st))) return e;
-        if ((e = launch_batch_level_walk(b, l, st))) return e;
-    }
-    return MDN_OK;
-}
-
 }  // namespace mdn
 
 namespace {
 
+int image_bank(const int32_t* bank, int i) { return bank ? bank[i] : 0; }
+
+// Launch list and tables of one batch: image i, of bank bank[i], uses the workspace ws[i]
+// (batch_image_ws bytes for its bank's depth, 256-aligned). The tables are appended to `tab` (host
+// bytes, every table 256-aligned) and each launch keeps its table's offset.
+void build_batch(const mdn_plan* p, const mdn_image* in, const mdn_image* out, const int32_t* bank,
+                 void* const* ws, int n, const int (*rows)[3], std::vector<char>& tab, BatchLaunch* bl) {
+    const int ncu = device_cus();
+    const int storage = p->storage;
+    std::vector<D2Image> d2((size_t)n * kMaxLevels);
+    std::vector<SelImage> sel((size_t)n * kMaxLevels);
+    std::vector<WalkImage> walk((size_t)n * kMaxLevels);
+    std::vector<TileImage> tile((size_t)n * kMaxLevels);
+    for (int i = 0; i < n; ++i) {
+        const size_t o = (size_t)i * kMaxLevels;
+        describe_cascade(in[i], out[i], ws[i], p->bank[image_bank(bank, i)].L, storage, rows, ncu, &d2[o], &sel[o],
+                         &walk[o], &tile[o]);
+    }
+    tab.clear();
+    bl->items.clear();
+    auto put = [&](const void* d, size_t bytes) {
+        const char* c = static_cast<const char*>(d);
+        tab.insert(tab.end(), c, c + bytes);
+    };
+    auto item = [&](int kind, int level, int b) {
+        BatchItem it;
+        memset(&it, 0, sizeof(it));
+        it.kind = kind;
+        it.level = level;
+        it.bank = b;
+        it.tab_off = tab.size();
+        it.z_dtype = level == 0 ? in[0].dtype : storage;
+        it.out_dtype = level == 0 ? out[0].dtype : storage;
+        it.out_color = level == 0 ? MDN_RGB : MDN_YCC;
+        return it;
+    };
+    auto close = [&](BatchItem& it) {
+        bl->items.push_back(it);
+        tab.resize(al256(tab.size()));
+    };
+    // pyramid steps l -> l + 1 over every image whose bank is deeper than l
+    for (int l = 0; l < p->Lmax; ++l) {
+        BatchItem it = item(0, l, -1);
+        int begin = 0, cnt = 0;
+        for (int i = 0; i < n; ++i) {
+            if (p->bank[image_bank(bank, i)].L <= l) continue;
+            D2Image d = d2[(size_t)i * kMaxLevels + l];
+            d.strip_begin = begin;
+            begin += strips_of(d);
+            put(&d, sizeof(d));
+            ++cnt;
+        }
+        if (!cnt) continue;
+        it.d2.n_imgs = cnt;
+        it.d2.n_strips = begin;
+        close(it);
+    }
+    // levels from the coarsest trained one down, bank by bank: an image's level l runs after its
+    // level l + 1, whatever the depth of its bank
+    for (int l = p->Lmax - 1; l >= 0; --l) {
+        for (int b = 0; b < p->n_banks; ++b) {
+            const PlanBank& pb = p->bank[b];
+            if (pb.L <= l) continue;
+            std::vector<int> imgs;
+            for (int i = 0; i < n; ++i)
+                if (image_bank(bank, i) == b) imgs.push_back(i);
+            if (imgs.empty()) continue;
+            const mdn_level& lv = pb.lv[l];
+            if (level_runs_tiled(lv, 3)) {
+                BatchItem it = item(3, l, b);
+                int begin = 0;
+                for (int i : imgs) {
+                    TileImage t = tile[(size_t)i * kMaxLevels + l];
+                    t.tile_begin = begin;
+                    begin += tiles_of(t);
+                    put(&t, sizeof(t));
+                }
+                it.lv = lv;
+                it.n_imgs = (int)imgs.size();
+                it.n_tiles = begin;
+                it.uc_color = l == pb.L - 1 ? MDN_RGB : MDN_YCC;
+                close(it);
+                continue;
+            }
+            BatchItem si = item(1, l, b);
+            int begin = 0;
+            for (int i : imgs) {
+                SelImage e = sel[(size_t)i * kMaxLevels + l];
+                e.strip_begin = begin;
+                begin += strips_of(e);
+                put(&e, sizeof(e));
+            }
+            si.sel = pb.selc[l];
+            si.sel.n_imgs = (int)imgs.size();
+            si.sel.n_strips = begin;
+            close(si);
+            BatchItem wi = item(2, l, b);
+            begin = 0;
+            for (int i : imgs) {
+                WalkImage w = walk[(size_t)i * kMaxLevels + l];
+                w.strip_begin = begin;
+                begin += strips_of(w);
+                put(&w, sizeof(w));
+            }
+            wi.walk.n_imgs = (int)imgs.size();
+            wi.walk.n_strips = begin;
+            wi.walk.coeffs = lv.coeffs;
+            wi.walk.coeff_dtype = lv.coeff_dtype;
+            wi.walk.K = level_buckets(lv);
+            close(wi);
+        }
+    }
+    bl->Lmax = p->Lmax;
+    bl->storage = storage;
+    bl->in_dtype = in[0].dtype;
+    bl->out_dtype = out[0].dtype;
+    bl->table_bytes = tab.size();
+}
+
+mdn_status launch_item(const BatchLaunch& bl, const BatchItem& it, hipStream_t st) {
+    const char* t = bl.tab_dev + it.tab_off;
+    switch (it.kind) {
+    case 0: {
+        D2Args a = it.d2;
+        a.imgs = reinterpret_cast<const D2Image*>(t);
+        return launch_down2_args(a, 3, it.z_dtype, bl.storage, st);
+    }
+    case 1: {
+        SelWalkArgs a = it.sel;
+        a.imgs = reinterpret_cast<const SelImage*>(t);
+        return launch_select_args(a, 3, it.z_dtype, st);
+    }
+    case 2: {
+        WalkArgs a = it.walk;
+        a.imgs = reinterpret_cast<const WalkImage*>(t);
+        return launch_walk_args(a, it.z_dtype, bl.storage, it.out_dtype, st);
+    }
+    default:
+        return launch_select_apply_table(it.lv, reinterpret_cast<const TileImage*>(t), it.n_imgs, it.n_tiles, 3,
+                                         it.z_dtype, bl.storage, it.uc_color, it.out_dtype, it.out_color, st);
+    }
+}
+
+// the launches of one kind group at level l: pyramid (0), selection (1), filtering (2: walk or tiled)
+mdn_status run_group(mdn_plan* p, int group, int l) {
+    for (const BatchItem& it : p->bl.items) {
+        if (it.level != l) continue;
+        const bool in = group == 0 ? it.kind == 0 : group == 1 ? it.kind == 1 : (it.kind == 2 || it.kind == 3);
+        if (!in) continue;
+        mdn_status e = launch_item(p->bl, it, p->stream);
+        if (e) return e;
+    }
+    return MDN_OK;
+}
+bool level_has_selection(const mdn_plan* p, int l) {
+    for (const BatchItem& it : p->bl.items)
+        if (it.level == l && it.kind == 1) return true;
+    return false;
+}
+
 // Carve the per-image workspaces out of the plan's workspace and build the launch tables.
-mdn_status prepare(mdn_plan* p, const mdn_image* in, const mdn_image* out, int n) {
-    const int L = p->L;
+mdn_status prepare(mdn_plan* p, const mdn_image* in, const mdn_image* out, const int32_t* bank, int n) {
     size_t need = 0;
-    for (int i = 0; i < n; ++i) need += batch_image_ws(in[i].width, in[i].height, L, p->storage);
+    for (int i = 0; i < n; ++i) need += batch_image_ws(in[i].width, in[i].height, p->bank[image_bank(bank, i)].L, p->storage);
     mdn_status st;
     if ((st = ensure_ws(p, need))) return st;
-    if ((st = ensure_tables(p, batch_table_bytes(n, L)))) return st;
-    if (hipStreamSynchronize(p->stream) != hipSuccess) return fail(MDN_EDEVICE, "plan: sync failed");
     std::vector<void*> ws(n);
     char* w = p->ws;
     for (int i = 0; i < n; ++i) {
         ws[i] = w;
-        w += batch_image_ws(in[i].width, in[i].height, L, p->storage);
+        w += batch_image_ws(in[i].width, in[i].height, p->bank[image_bank(bank, i)].L, p->storage);
     }
     int rows[kMaxLevels][3];
-    for (int l = 0; l < L; ++l) {
+    for (int l = 0; l < p->Lmax; ++l) {
         rows[l][0] = p->rows_d2[l];
         rows[l][1] = p->rows_sel[l];
         rows[l][2] = p->rows_walk[l];
     }
-    if ((st = build_batch(p->lv, p->selc, L, p->storage, in, out, ws.data(), n, p->tuned ? rows : nullptr,
-                          p->tab_host, p->tab_dev, &p->bl)))
-        return st;
-    if (hipMemcpyAsync(p->tab_dev, p->tab_host, p->bl.table_bytes, hipMemcpyHostToDevice, p->stream) != hipSuccess)
+    std::vector<char> tab;
+    build_batch(p, in, out, bank, ws.data(), n, p->tuned ? rows : nullptr, tab, &p->bl);
+    if ((st = ensure_tables(p, tab.size() ? tab.size() : 256))) return st;
+    if (hipStreamSynchronize(p->stream) != hipSuccess) return fail(MDN_EDEVICE, "plan: sync failed");
+    memcpy(p->tab_host, tab.data(), tab.size());
+    p->bl.tab_dev = p->tab_dev;
+    if (tab.size() && hipMemcpyAsync(p->tab_dev, p->tab_host, tab.size(), hipMemcpyHostToDevice, p->stream) != hipSuccess)
         return fail(MDN_EDEVICE, "plan: table upload failed");
     p->tables_valid = true;
     return MDN_OK;
 }
 
-mdn_status run_d2(mdn_plan* p, int l) { return launch_batch_level_d2(p->bl, l, p->stream); }
-mdn_status run_sel(mdn_plan* p, int l) { return launch_batch_level_sel(p->bl, l, p->stream); }
-mdn_status run_walk(mdn_plan* p, int l) { return launch_batch_level_walk(p->bl, l, p->stream); }
-mdn_status launch_all(mdn_plan* p) { return launch_batch(p->bl, p->stream); }
+mdn_status run_d2(mdn_plan* p, int l) { return run_group(p, 0, l); }
+mdn_status run_sel(mdn_plan* p, int l) { return run_group(p, 1, l); }
+mdn_status run_walk(mdn_plan* p, int l) { return run_group(p, 2, l); }
+mdn_status launch_all(mdn_plan* p) {
+    for (const BatchItem& it : p->bl.items) {
+        mdn_status e = launch_item(p->bl, it, p->stream);
+        if (e) return e;
+    }
+    return MDN_OK;
+}
 
 void drop_graph(mdn_plan* p) {
     if (p->exec) hipGraphExecDestroy(p->exec);
@@ -380,12 +435,14 @@ void drop_graph(mdn_plan* p) {
     p->graph = nullptr;
 }
 
-mdn_status check_batch(const mdn_plan* p, const mdn_image* in, const mdn_image* out, int n) {
+mdn_status check_batch(const mdn_plan* p, const mdn_image* in, const mdn_image* out, const int32_t* bank, int n) {
     if (n < 1 || n > p->max_images) return fail(MDN_EINVAL, "batch: n must be 1..%d", p->max_images);
     if (!in || !out) return fail(MDN_EINVAL, "batch: null image arrays");
     for (int i = 0; i < n; ++i) {
         const mdn_image& a = in[i];
         const mdn_image& b = out[i];
+        if (bank && (bank[i] < 0 || bank[i] >= p->n_banks))
+            return fail(MDN_EINVAL, "batch: image %d: bank %d, the plan has %d", i, bank[i], p->n_banks);
         if (a.channels != 3 || a.color != MDN_RGB || b.channels != 3 || b.color != MDN_RGB)
             return fail(MDN_EINVAL, "batch: images must be RGB");
         if (a.width < 1 || a.height < 1 || a.width != b.width || a.height != b.height)
@@ -408,41 +465,51 @@ mdn_status check_batch(const mdn_plan* p, const mdn_image* in, const mdn_image* 
 
 extern "C" {
 
-mdn_status mdn_plan_create(const mdn_bank* bank, int32_t storage, int32_t max_images, mdn_plan** out) {
+mdn_status mdn_plan_create_banks(const mdn_bank* banks, int32_t n_banks, int32_t storage, int32_t max_images,
+                                 mdn_plan** out) {
     clear_error();
     if (!out) return fail(MDN_EINVAL, "plan: null out");
     *out = nullptr;
-    if (!bank || bank->levels < 1 || bank->levels > kMaxLevels || !bank->level)
-        return fail(MDN_EINVAL, "plan: need 1..%d bank levels", kMaxLevels);
+    if (!banks || n_banks < 1 || n_banks > kMaxPlanBanks) return fail(MDN_EINVAL, "plan: need 1..%d banks", kMaxPlanBanks);
     if (storage != MDN_F16 && storage != MDN_F32) return fail(MDN_EINVAL, "plan: unknown storage dtype");
     if (max_images < 1 || max_images > 4096) return fail(MDN_EINVAL, "plan: max_images must be 1..4096");
-    for (int l = 0; l < bank->levels; ++l) {
-        const mdn_level& lv = bank->level[l];
-        mdn_status st = validate_level(&lv, 3);
-        if (!st && !lv.t_s && lv.q_s > 1) st = fail(MDN_EINVAL, "plan: null thresholds");
-        if (st) return st;
-        if (lv.radius_f < 1) return fail(MDN_ENOTSUP, "plan: the batched form runs multiscale banks");
-        const bool walk = lv.coeff_dtype == MDN_F16 && walk_supported(lv, 3);
-        if (walk && lv.selector == MDN_SELECT_COARSE)
-            return fail(MDN_ENOTSUP, "plan: float16 7x7/7x7 levels that select on the coarser output are not batched");
-        if (!walk && !level_runs_tiled(lv, 3))
-            return fail(MDN_ENOTSUP, "plan: float32 banks that fit in LDS one channel at a time are not batched");
+    for (int b = 0; b < n_banks; ++b) {
+        const mdn_bank* bank = &banks[b];
+        if (bank->levels < 1 || bank->levels > kMaxLevels || !bank->level)
+            return fail(MDN_EINVAL, "plan: bank %d: need 1..%d levels", b, kMaxLevels);
+        for (int l = 0; l < bank->levels; ++l) {
+            const mdn_level& lv = bank->level[l];
+            mdn_status st = validate_level(&lv, 3);
+            if (!st && !lv.t_s && lv.q_s > 1) st = fail(MDN_EINVAL, "plan: null thresholds");
+            if (st) return st;
+            if (lv.radius_f < 1) return fail(MDN_ENOTSUP, "plan: the batched form runs multiscale banks");
+            const bool walk = lv.coeff_dtype == MDN_F16 && walk_supported(lv, 3);
+            if (walk && lv.selector == MDN_SELECT_COARSE)
+                return fail(MDN_ENOTSUP, "plan: float16 7x7/7x7 levels that select on the coarser output are not batched");
+            if (!walk && !level_runs_tiled(lv, 3))
+                return fail(MDN_ENOTSUP, "plan: float32 banks that fit in LDS one channel at a time are not batched");
+        }
     }
     mdn_status ist = init_walk_kernels();
     if (ist) return ist;
     mdn_plan* p = new mdn_plan();
     hipGetDevice(&p->device);
     p->storage = storage;
-    p->L = bank->levels;
+    p->n_banks = n_banks;
     p->max_images = max_images;
-    for (int l = 0; l < p->L; ++l) {
-        p->lv[l] = bank->level[l];
-        for (int j = 0; j < p->lv[l].q_s - 1; ++j) p->thr[l][0][j] = p->lv[l].t_s[j];
-        for (int j = 0; j < p->lv[l].q_c - 1; ++j) p->thr[l][1][j] = p->lv[l].t_c[j];
-        p->lv[l].t_s = p->thr[l][0];
-        p->lv[l].t_c = p->thr[l][1];
-        memset(&p->selc[l], 0, sizeof(SelWalkArgs));
-        fill_sel_consts(p->lv[l], p->selc[l]);
+    for (int b = 0; b < n_banks; ++b) {
+        PlanBank& pb = p->bank[b];
+        pb.L = banks[b].levels;
+        p->Lmax = pb.L > p->Lmax ? pb.L : p->Lmax;
+        for (int l = 0; l < pb.L; ++l) {
+            pb.lv[l] = banks[b].level[l];
+            for (int j = 0; j < pb.lv[l].q_s - 1; ++j) pb.thr[l][0][j] = pb.lv[l].t_s[j];
+            for (int j = 0; j < pb.lv[l].q_c - 1; ++j) pb.thr[l][1][j] = pb.lv[l].t_c[j];
+            pb.lv[l].t_s = pb.thr[l][0];
+            pb.lv[l].t_c = pb.thr[l][1];
+            memset(&pb.selc[l], 0, sizeof(SelWalkArgs));
+            fill_sel_consts(pb.lv[l], pb.selc[l]);
+        }
     }
     if (hipStreamCreateWithFlags(&p->stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&p->ev_in, hipEventDisableTiming) != hipSuccess ||
@@ -452,6 +519,10 @@ mdn_status mdn_plan_create(const mdn_bank* bank, int32_t storage, int32_t max_im
     }
     *out = p;
     return MDN_OK;
+}
+
+mdn_status mdn_plan_create(const mdn_bank* bank, int32_t storage, int32_t max_images, mdn_plan** out) {
+    return mdn_plan_create_banks(bank, 1, storage, max_images, out);
 }
 
 mdn_status mdn_plan_destroy(mdn_plan* p) {
@@ -468,19 +539,19 @@ mdn_status mdn_plan_destroy(mdn_plan* p) {
     return MDN_OK;
 }
 
-mdn_status mdn_plan_autotune(mdn_plan* p, const mdn_image* in, const mdn_image* out, int32_t n, int32_t* rows_out,
-                             void* stream) {
+mdn_status mdn_plan_autotune(mdn_plan* p, const mdn_image* in, const mdn_image* out, const int32_t* bank, int32_t n,
+                             int32_t* rows_out, void* stream) {
     clear_error();
     if (!p) return fail(MDN_EINVAL, "plan: null");
-    mdn_status st = check_batch(p, in, out, n);
+    mdn_status st = check_batch(p, in, out, bank, n);
     if (st) return st;
     hipStream_t cs = static_cast<hipStream_t>(stream);
     if (hipEventRecord(p->ev_in, cs) != hipSuccess || hipStreamWaitEvent(p->stream, p->ev_in, 0) != hipSuccess)
         return fail(MDN_EDEVICE, "plan: stream ordering failed");
     drop_graph(p);
     p->tuned = false;
-    if ((st = prepare(p, in, out, n))) return st;
-    const int L = p->L;
+    if ((st = prepare(p, in, out, bank, n))) return st;
+    const int L = p->Lmax;
     hipEvent_t e0, e1;
     hipEventCreate(&e0);
     hipEventCreate(&e1);
@@ -516,7 +587,7 @@ mdn_status mdn_plan_autotune(mdn_plan* p, const mdn_image* in, const mdn_image* 
         float best = 1e30f;
         for (int c : c_d2) {
             p->rows_d2[l] = c;
-            if ((st = prepare(p, in, out, n))) break;
+            if ((st = prepare(p, in, out, bank, n))) break;
             const float ms = time_it([&] { run_d2(p, l); });
             if (ms < best) {
                 best = ms;
@@ -524,19 +595,20 @@ mdn_status mdn_plan_autotune(mdn_plan* p, const mdn_image* in, const mdn_image* 
             }
         }
         p->rows_d2[l] = best_d2[l];
-        if (!st) st = prepare(p, in, out, n);
+        if (!st) st = prepare(p, in, out, bank, n);
         if (!st) st = run_d2(p, l);
     }
     for (int l = L - 1; l >= 0 && !st; --l) {
-        if (p->bl.tiled[l]) {
-            // fixed 64 x 16 tiles with the selection inline: nothing to tune, run the level once
+        if (!level_has_selection(p, l)) {
+            // every bank's level runs the tiled kernel (fixed 64 x 16 tiles, selection inline):
+            // nothing to tune, run the level once
             st = run_walk(p, l);
             continue;
         }
         float best = 1e30f;
         for (int c : c_sel) {
             p->rows_sel[l] = c;
-            if ((st = prepare(p, in, out, n))) break;
+            if ((st = prepare(p, in, out, bank, n))) break;
             const float ms = time_it([&] { run_sel(p, l); });
             if (ms < best) {
                 best = ms;
@@ -548,7 +620,7 @@ mdn_status mdn_plan_autotune(mdn_plan* p, const mdn_image* in, const mdn_image* 
         best = 1e30f;
         for (int c : c_walk) {
             p->rows_walk[l] = c;
-            if ((st = prepare(p, in, out, n))) break;
+            if ((st = prepare(p, in, out, bank, n))) break;
             const float ms = time_it([&] { run_walk(p, l); });
             if (ms < best) {
                 best = ms;
@@ -556,7 +628,7 @@ mdn_status mdn_plan_autotune(mdn_plan* p, const mdn_image* in, const mdn_image* 
             }
         }
         p->rows_walk[l] = best_walk[l];
-        if (!st) st = prepare(p, in, out, n);
+        if (!st) st = prepare(p, in, out, bank, n);
         if (!st) st = run_sel(p, l);
         if (!st) st = run_walk(p, l);
     }
@@ -576,27 +648,27 @@ mdn_status mdn_plan_autotune(mdn_plan* p, const mdn_image* in, const mdn_image* 
     return check_launch("autotune");
 }
 
-mdn_status mdn_plan_kernel_times(mdn_plan* p, const mdn_image* in, const mdn_image* out, int32_t n, int32_t reps,
-                                 float* us_out, void* stream) {
+mdn_status mdn_plan_kernel_times(mdn_plan* p, const mdn_image* in, const mdn_image* out, const int32_t* bank,
+                                 int32_t n, int32_t reps, float* us_out, void* stream) {
     clear_error();
     if (!p) return fail(MDN_EINVAL, "plan: null");
-    mdn_status st = check_batch(p, in, out, n);
+    mdn_status st = check_batch(p, in, out, bank, n);
     if (st) return st;
     if (reps < 1 || reps > 1000) return fail(MDN_EINVAL, "plan: reps must be 1..1000");
     if (!us_out) return fail(MDN_EINVAL, "plan: null output");
     hipStream_t cs = static_cast<hipStream_t>(stream);
     if (hipEventRecord(p->ev_in, cs) != hipSuccess || hipStreamWaitEvent(p->stream, p->ev_in, 0) != hipSuccess)
         return fail(MDN_EDEVICE, "plan: stream ordering failed");
-    std::vector<uint64_t> sig = signature(in, out, n);
+    std::vector<uint64_t> sig = signature(in, out, bank, n);
     if (!(p->tables_valid && sig == p->sig)) {
         drop_graph(p);
-        if ((st = prepare(p, in, out, n))) return st;
+        if ((st = prepare(p, in, out, bank, n))) return st;
         p->sig = sig;
     }
     // the launches of one batch in their usual order, each between two events on the plan's stream
     // and started on an idle stream (events recorded between back-to-back launches have been seen to
     // miss part of the second launch)
-    const int L = p->L, nk = 3 * L;
+    const int L = p->Lmax, nk = 3 * L;
     std::vector<hipEvent_t> ev(2 * (size_t)nk * reps, nullptr);
     for (auto& e : ev)
         if (hipEventCreate(&e) != hipSuccess) {
@@ -638,20 +710,20 @@ mdn_status mdn_plan_kernel_times(mdn_plan* p, const mdn_image* in, const mdn_ima
     return check_launch("kernel_times");
 }
 
-mdn_status mdn_denoise_batch(mdn_plan* p, const mdn_image* in, const mdn_image* out, int32_t n, int32_t use_graph,
-                             void* stream) {
+mdn_status mdn_denoise_batch(mdn_plan* p, const mdn_image* in, const mdn_image* out, const int32_t* bank, int32_t n,
+                             int32_t use_graph, void* stream) {
     clear_error();
     if (!p) return fail(MDN_EINVAL, "plan: null");
-    mdn_status st = check_batch(p, in, out, n);
+    mdn_status st = check_batch(p, in, out, bank, n);
     if (st) return st;
     hipStream_t cs = static_cast<hipStream_t>(stream);
     if (hipEventRecord(p->ev_in, cs) != hipSuccess || hipStreamWaitEvent(p->stream, p->ev_in, 0) != hipSuccess)
         return fail(MDN_EDEVICE, "plan: stream ordering failed");
-    std::vector<uint64_t> sig = signature(in, out, n);
+    std::vector<uint64_t> sig = signature(in, out, bank, n);
     const bool same = p->tables_valid && sig == p->sig;
     if (!same) {
         drop_graph(p);
-        if ((st = prepare(p, in, out, n))) return st;
+        if ((st = prepare(p, in, out, bank, n))) return st;
         p->sig = sig;
     }
     if (use_graph) {

@@ -5,6 +5,8 @@
 
 #include "mdn_internal.h"
 
+#include <vector>
+
 namespace mdn {
 
 constexpr int kWalkLanesOut = 58;   // filtering: output columns per wave (3-column halo each side)
@@ -94,22 +96,31 @@ mdn_status launch_down2_args(const D2Args& a, int channels, int in_dtype, int ou
 
 // ---------------------------------------------------------------- batched cascade
 constexpr int kMaxLevels = 8;
+constexpr int kMaxPlanBanks = 8;
+
+// One launch of a batch: a pyramid step (level l -> l+1, every image deep enough), or the selection
+// pass, the filtering walk or the tiled select-and-filter kernel of level l for the images of one
+// bank. The table of the launch sits at tab_off in the batch's table buffer.
+struct BatchItem {
+    int kind;                    // 0 pyramid, 1 selection, 2 filtering walk, 3 tiled
+    int level, bank;
+    size_t tab_off;              // table of the launch in the batch's table buffer
+    D2Args d2;
+    SelWalkArgs sel;
+    WalkArgs walk;
+    mdn_level lv;                // tiled launches
+    const TileImage* tiles;
+    int32_t n_imgs, n_tiles, z_dtype, uc_color, out_dtype, out_color;
+};
 
 struct BatchLaunch {
-    int L, storage, in_dtype, out_dtype;
+    int Lmax, storage, in_dtype, out_dtype;
     size_t table_bytes;
-    D2Args d2[kMaxLevels];
-    SelWalkArgs sel[kMaxLevels];
-    WalkArgs walk[kMaxLevels];
-    // levels filtered by the tiled kernel (selection inline): one launch over the level's tile table
-    bool tiled[kMaxLevels];
-    mdn_level lv[kMaxLevels];
-    const TileImage* tiles[kMaxLevels];
-    int32_t n_imgs, n_tiles[kMaxLevels];
+    const char* tab_dev;               // device copy of the tables
+    std::vector<BatchItem> items;      // in launch order
 };
 
 size_t batch_image_ws(int w, int h, int L, int storage);
-size_t batch_table_bytes(int n, int L);
 // tile: per-level descriptors for the tiled kernel, or null when not wanted
 void describe_cascade(const mdn_image& in, const mdn_image& out, void* ws, int L, int storage, const int (*rows)[3],
                       int ncu, D2Image* d2, SelImage* sel, WalkImage* walk, TileImage* tile = nullptr);
@@ -117,12 +128,5 @@ int tiles_of(const TileImage& t);
 int strips_of(const D2Image& d);
 int strips_of(const SelImage& d);
 int strips_of(const WalkImage& d);
-mdn_status build_batch(const mdn_level* lv, const SelWalkArgs* selc, int L, int storage, const mdn_image* in,
-                       const mdn_image* out, void* const* ws, int n, const int (*rows)[3], char* tab_host,
-                       char* tab_dev, BatchLaunch* bl);
-mdn_status launch_batch_level_d2(const BatchLaunch& b, int l, hipStream_t st);
-mdn_status launch_batch_level_sel(const BatchLaunch& b, int l, hipStream_t st);
-mdn_status launch_batch_level_walk(const BatchLaunch& b, int l, hipStream_t st);
-mdn_status launch_batch(const BatchLaunch& b, hipStream_t st);
 
 }  // namespace mdn

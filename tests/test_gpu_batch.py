@@ -139,3 +139,55 @@ def test_batch_with_many_strips_per_wave_equals_per_image():
         want = M.denoise(z, gb, storage=M.F16)
         assert torch.equal(outs[i], want), f"image {i} differs"
     plan.close()
+
+
+def _paper_bank(M, torch, L, rf, rg, seed):
+    """4096-bucket bank of the paper's configuration (Section 5) with stand-in coefficients and the
+    equal-population thresholds of seeded scenes at each level."""
+    import oracle as O
+    zs0 = [synth.noisy_pair(300 + i, 160, 160, 3, 25)[0].astype(np.float64) for i in range(3)]
+    lvs = []
+    for lev in range(L):
+        f = [O.level_features(O.build_pyramid(z, lev + 1)[lev]) for z in zs0]
+        t_s = O.thresholds_from_features(np.concatenate([x[0] for x in f]), 16)
+        t_c = O.thresholds_from_features(np.concatenate([x[1] for x in f]), 16)
+        co = synth.random_bank_coeffs(seed + lev, 4096, 3, (2 * rf + 1) ** 2, (2 * rg + 1) ** 2)
+        lvs.append(M.Level(16, t_s, t_c, rg, rf, torch.from_numpy(co).to(torch.float16).cuda(), 3))
+    return M.Bank(lvs)
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_with_a_bank_per_image(use_graph):
+    """Every image names its bank (the per-image bank[] of the batched call): three banks of
+    different depth and kernels in one plan (a 4-level column-walk bank, a 3-level 4096-bucket bank
+    with 5x5 / 3x3 filters, a 5-level 4096-bucket bank with 7x7 / 5x5 filters); each output equals
+    mdn_denoise with that image's bank, bit for bit, eagerly and from graph replays, after autotuning."""
+    import torch
+    import paper_1802_06130_amd as M
+    print(f"batch with a bank per image, graph={use_graph}", flush=True)
+    gb, zs = _setup()
+    banks = [gb, _paper_bank(M, torch, 2, 1, 2, 90), _paper_bank(M, torch, 4, 2, 3, 95)]
+    which = [i % 3 for i in range(len(zs))]
+    want = [M.denoise(z, banks[b], storage=M.F16).cpu().numpy() for z, b in zip(zs, which)]
+    plan = M.Plan(banks, M.F16, max_images=16)
+    assert plan.levels == 4
+    rows = plan.autotune(zs, banks=which)
+    outs = [torch.empty_like(z) for z in zs]
+    for rep in range(3):
+        for o in outs:
+            o.fill_(-1.0)
+        plan.denoise_batch(zs, outs, use_graph=use_graph, banks=which)
+        torch.cuda.synchronize()
+        for i, (o, w) in enumerate(zip(outs, want)):
+            assert np.array_equal(o.cpu().numpy(), w), f"rep {rep}: image {i} {SIZES[i]} bank {which[i]} differs"
+    kt = plan.kernel_times(zs, outs, reps=1, banks=which)
+    print(f"  rows {rows}; kernel us per level {kt}", flush=True)
+    # the same images with the banks exchanged: a new signature, new tables and graph
+    which2 = [(b + 1) % 3 for b in which]
+    plan.denoise_batch(zs, outs, use_graph=use_graph, banks=which2)
+    torch.cuda.synchronize()
+    for i, (z, o, b) in enumerate(zip(zs, outs, which2)):
+        assert np.array_equal(o.cpu().numpy(), M.denoise(z, banks[b], storage=M.F16).cpu().numpy())
+    with pytest.raises(M.MdnError):
+        plan.denoise_batch(zs, outs, banks=[3] * len(zs))
+    plan.close()
