@@ -83,6 +83,45 @@ def test_gram_multiscale_rgb(precision, tol):
     print(f"  worst ratio {worst:.3g}")
 
 
+def _gap_thresholds(f, q):
+    """q - 1 thresholds near the feature's quantiles, each the midpoint of the widest gap between
+    neighbouring sorted values in a small window, so that no pixel sits within rounding of one."""
+    v = np.sort(np.asarray(f, dtype=np.float64).ravel())
+    t = []
+    for j in range(1, q):
+        i = int(j * len(v) / q)
+        lo, hi = max(0, i - 8), min(len(v) - 1, i + 8)
+        k = lo + int(np.argmax(np.diff(v[lo:hi + 1])))
+        t.append(0.5 * (v[k] + v[k + 1]))
+    return t
+
+
+@pytest.mark.parametrize("phases", [1, 4])
+def test_gram_with_many_buckets(phases):
+    """16384 buckets (the grouping's counters in LDS) and 65536 with phases (the largest K, 16-bit
+    keys, counters in global memory): the normal equations still match bucket by bucket."""
+    import paper_1802_06130_amd as M
+    torch = _torch()
+    q_theta, q = 64, 16
+    K = q_theta * q * q * phases
+    print(f"gram grey K={K}", flush=True)
+    pairs = _pairs(3, 96, 1, seed0=40)
+    feats = [O.level_features(z.astype(np.float64)) for z, _ in pairs]
+    t_s = _gap_thresholds(np.concatenate([f[0].ravel() for f in feats]), q)
+    t_c = _gap_thresholds(np.concatenate([f[1].ravel() for f in feats]), q)
+    st = O.GramStats.zeros(K, 1, 9)
+    for z, u in pairs:
+        s = O.select(z.astype(np.float64), q_theta, t_s, t_c, phases=phases)
+        O.accumulate_level(st, s, O.to_filter_space(z), O.to_filter_space(u), 1)
+    assert np.count_nonzero(st.n) > 1000
+    g = M.Gram(K, 1, 1)
+    sel = M.Level(q_theta, t_s, t_c, 1, None, torch.zeros((K, 1, 9), device="cuda"), 1, phases=phases)
+    for z, u in pairs:
+        M.train_accumulate(g, _dev(z), _dev(u), sel, precision=0)
+    worst = _check_gram(g, st, 2e-5)
+    print(f"  worst ratio {worst:.3g}")
+
+
 @pytest.mark.parametrize("precision,tol", [(0, 2e-5), (1, 2e-4)])
 def test_gram_cross_channel_147(precision, tol):
     """Cross-channel layout (x = the three channels' 7x7 patches, D = 147, three right-hand sides)
