@@ -96,16 +96,17 @@ def _gap_thresholds(f, q):
     return t
 
 
-@pytest.mark.parametrize("phases", [1, 4])
-def test_gram_with_many_buckets(phases):
-    """16384 buckets (the grouping's counters in LDS) and 65536 with phases (the largest K, 16-bit
-    keys, counters in global memory): the normal equations still match bucket by bucket."""
+@pytest.mark.parametrize("q_theta,q,phases,H,W,n", [(64, 16, 1, 96, 96, 3), (64, 16, 4, 96, 96, 3),
+                                                     (16, 16, 1, 512, 768, 1)])
+def test_gram_with_many_buckets(q_theta, q, phases, H, W, n):
+    """The bucket grouping at its limits: 16384 buckets and 65536 with phases (the largest K, 16-bit
+    keys, running positions in global memory), and 4096 buckets over 393216 pixels (slices of 2048
+    pixels, 768 scan blocks, positions in LDS): the normal equations still match bucket by bucket."""
     import paper_1802_06130_amd as M
     torch = _torch()
-    q_theta, q = 64, 16
     K = q_theta * q * q * phases
-    print(f"gram grey K={K}", flush=True)
-    pairs = _pairs(3, 96, 1, seed0=40)
+    print(f"gram grey K={K} {H}x{W} x{n}", flush=True)
+    pairs = _pairs(n, H, 1, seed0=40) if H == W else [synth.noisy_pair(40 + i, H, W, 1, 25.0) for i in range(n)]
     feats = [O.level_features(z.astype(np.float64)) for z, _ in pairs]
     t_s = _gap_thresholds(np.concatenate([f[0].ravel() for f in feats]), q)
     t_c = _gap_thresholds(np.concatenate([f[1].ravel() for f in feats]), q)
