@@ -151,7 +151,7 @@ template <typename TZ, typename TS, int C, bool LUMA, int QS, int QC, int MQ, in
 __global__ __launch_bounds__(64 * kWaves, MDN_SEL_WAVES_PER_SIMD) void k_select_walk(SelWalkArgs a) {
     static_assert(!LUMA || C == 3, "the luma selector reads RGB");
     constexpr int NC = LUMA ? 1 : C;                             // channels of the selector image
-    using RowT = std::conditional_t<LUMA, double, float>;
+    using RowT = double;                     // rows converted to float64 once, at load
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     __shared__ BoundaryTable bt;
