@@ -227,7 +227,7 @@ mdn_status mdn_gram_dims(const mdn_gram* g, int32_t* D, int32_t* nrhs, int32_t* 
 mdn_status mdn_gram_zero(const mdn_gram* g, void* stream);
 
 /* Bytes of workspace mdn_train_accumulate needs for this gram and a width x height level
- * (float32 planes, the selector map, the bucket sort and the per-segment partial tiles). */
+ * (float32 planes, the selector map, the bucket grouping and the per-work-item partial tiles). */
 mdn_status mdn_train_workspace_size(const mdn_gram* g, int32_t width, int32_t height, size_t* bytes);
 
 /* Add one training pair's samples at one level to the normal equations (Eq. (8)):
@@ -235,7 +235,8 @@ mdn_status mdn_train_workspace_size(const mdn_gram* g, int32_t width, int32_t he
  * u_coarse: coarser output u^{l+1} (YCbCr, or RGB for the coarsest pyramid level), NULL for the
  *           single-scale or cross-channel layouts;
  * target:   clean level u^l (RGB or grey), same size as z.
- * Samples are taken in raster order, so repeated calls are bitwise reproducible. */
+ * Samples are grouped by bucket in raster order and summed in a fixed order, so repeated calls on
+ * one device are bitwise reproducible (the work split follows the device's compute-unit count). */
 mdn_status mdn_train_accumulate(const mdn_gram* g, const mdn_image* z, const mdn_image* u_coarse,
                                 const mdn_image* target, const mdn_level* sel, int32_t precision,
                                 void* ws, size_t ws_bytes, void* stream);
