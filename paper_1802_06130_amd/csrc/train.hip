@@ -171,6 +171,11 @@ static_assert(wave_tiles_cover(1) && wave_tiles_cover(2) && wave_tiles_cover(3) 
 // (float64), and add them to the accumulators (256 threads); the result does not depend on timing.
 // An off-diagonal tile also goes, transposed through LDS, to the lower triangle, so that both
 // halves of G are written along its rows.
+// Columns of tile (P, Q) that hold features: 32, or fewer in the last column panel (the augmented
+// features end at Daug). A tile with nq < 32 columns is stored compactly in its 1024-float slot:
+// entry r of lane l (l mod 32 < nq) at r 2nq + (l / 32) nq + l mod 32, 32 nq floats in all.
+__host__ __device__ inline int tile_cols(int T, int Q, int daug) { return Q == T - 1 ? daug - 32 * Q : 32; }
+
 __device__ void add_partials(const GramArgs& a, int T, int t, int k, int sys_c, int sys, int i0, int i1, int spk) {
     __shared__ double tr[32][33];
     const int NT = T * (T + 1) / 2;
@@ -181,7 +186,8 @@ __device__ void add_partials(const GramArgs& a, int T, int t, int k, int sys_c, 
     double* yy = a.yy + (int64_t)sys * a.nrhs;
     int P, Q;
     tile_pq(T, t, &P, &Q);
-    for (int e = threadIdx.x; e < 1024; e += 256) {
+    const int nq = tile_cols(T, Q, a.Daug);
+    for (int e = threadIdx.x; e < 32 * nq; e += 256) {
         // kReduceBatch items' partials are loaded at once (past the last item, the last one is
         // re-read), then summed in item order
         double v = 0.0;
@@ -196,9 +202,9 @@ __device__ void add_partials(const GramArgs& a, int T, int t, int k, int sys_c, 
             for (int j = 0; j < kReduceBatch; ++j)
                 if (ib + j < i1) v += (double)pv[j];
         }
-        // accumulator layout of a 32x32 MFMA tile: entry r of lane
-        const int r = e >> 6, lane = e & 63;
-        const int pl = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3), ql = lane & 31;
+        // accumulator layout of a 32x32 MFMA tile: entry r of lane (stored compactly when nq < 32)
+        const int r = e / (2 * nq), kq = e - r * 2 * nq, half = kq >= nq ? 1 : 0, ql = kq - half * nq;
+        const int pl = 8 * (r >> 2) + 4 * half + (r & 3);
         const int p = P * 32 + pl, q = Q * 32 + ql;
         tr[ql][pl] = v;
         if (p >= a.Daug || q >= a.Daug) continue;
@@ -212,7 +218,7 @@ __device__ void add_partials(const GramArgs& a, int T, int t, int k, int sys_c, 
     }
     if (P != Q && Q * 32 < D) {
         __syncthreads();
-        for (int e = threadIdx.x; e < 1024; e += 256) {
+        for (int e = threadIdx.x; e < 32 * nq; e += 256) {
             const int ql = e >> 5, pl = e & 31;
             const int p = P * 32 + pl, q = Q * 32 + ql;
             if (p < D && q < D) G[(int64_t)q * D + p] += tr[ql][pl];
@@ -402,8 +408,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 4))) voi
 #pragma unroll
         for (int i = 0; i < L.n; ++i) {
             const int t = tile_number(T, L.p[i], L.q[i]);
+            const int nq = tile_cols(T, L.q[i], daug);
+            if (nq == 32) {
 #pragma unroll
-            for (int r = 0; r < 16; ++r) part[t * 1024 + r * 64 + lane] = acc[i][r];
+                for (int r = 0; r < 16; ++r) part[t * 1024 + r * 64 + lane] = acc[i][r];
+            } else if ((lane & 31) < nq) {
+                // last column panel: only its feature columns, compactly
+                const int o = t * 1024 + (lane >> 5) * nq + (lane & 31);
+#pragma unroll
+                for (int r = 0; r < 16; ++r) part[o + r * 2 * nq] = acc[i][r];
+            }
         }
     };
     switch (wave) {
