@@ -74,6 +74,14 @@ struct P3 {
     double A, B, C;
 };
 
+// a pointer every lane holds alike, moved to scalar registers
+template <typename T> __device__ __forceinline__ T* uniform_ptr(T* p) {
+    const uint64_t u = (uint64_t)p;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+    return (T*)(((uint64_t)hi << 32) | lo);
+}
+
 template <int I>
 using IC = std::integral_constant<int, I>;
 template <typename F, int... Is>
@@ -103,8 +111,9 @@ __device__ __forceinline__ int bucket(double a, double b, double c, const SelWal
 #pragma unroll
     for (int j = 0; j < (QS ? QS : kMaxThr + 1) - 1; ++j) {
         if (!QS && j >= q_s - 1) break;
+        // d <= 0 or m2 >= d^2, in one test: d |d| is -d^2 <= 0 <= m2 when d <= 0 (exact)
         const double d = 2.0 * sp.s_lim[j] - tr;
-        qs += (d <= 0.0 || m2 >= d * d) ? 1 : 0;
+        qs += (m2 >= d * fabs(d)) ? 1 : 0;
     }
     int qc = 0;
     const double tr2 = tr * tr;
@@ -187,7 +196,9 @@ __global__ __launch_bounds__(64 * kWaves, MDN_SEL_WAVES_PER_SIMD) void k_select_
         const bool out_lane = lane >= 3 && lane < 3 + kLanesOut && x < W;
         const int lane_x0 = 3 - xs, lane_xw = W - 1 - xs + 3;
         const bool fix_left = lane_x0 >= 0, fix_right = lane_xw <= 63;
-        const TZ* zb = static_cast<const TZ*>(im.z);
+        // image planes and selector map: wave-uniform, kept in scalar registers
+        const TZ* zb = uniform_ptr(static_cast<const TZ*>(im.z));
+        TS* sout = uniform_ptr(static_cast<TS*>(im.s));
         const uint32_t zrow = (uint32_t)im.z_row, zpl = (uint32_t)im.z_plane;
 
         // a row of the selector image: the channels as loaded, or the float64 luma of RGB
@@ -290,7 +301,7 @@ __global__ __launch_bounds__(64 * kWaves, MDN_SEL_WAVES_PER_SIMD) void k_select_
                 const double sc = (((hr[0].C + hr[1].C) + hr[2].C) + hr[3].C) + hr[4].C;
                 int s = bucket<QS, QC, MQ, NSTEP>(sa, sb, sc, a, bt);
                 if (a.phases == 4) s = 4 * s + ((y & 1) << 1) + (x & 1);
-                if (out_lane && y < ye) *((MDN_GLOBAL TS*)im.s + (uint32_t)y * (uint32_t)im.s_pitch + (uint32_t)x) = (TS)s;
+                if (out_lane && y < ye) *((MDN_GLOBAL TS*)sout + (uint32_t)y * (uint32_t)im.s_pitch + (uint32_t)x) = (TS)s;
             }, std::make_integer_sequence<int, 10>{});
         }
     }
