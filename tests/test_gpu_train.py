@@ -124,6 +124,32 @@ def test_gram_with_many_buckets(q_theta, q, phases, H, W, n):
 
 
 @pytest.mark.parametrize("precision,tol", [(0, 2e-5), (1, 2e-4)])
+@pytest.mark.parametrize("H,W", [(1, 1), (2, 3), (7, 1), (17, 33), (66, 130)])
+def test_gram_multiscale_rgb_small_and_ragged(H, W, precision, tol):
+    """Single pixels, slivers and sizes with ragged 64-sample chunks: one work item or a few, slices
+    of the grouping shorter than a wave, margins wider than the image."""
+    import paper_1802_06130_amd as M
+    torch = _torch()
+    print(f"gram rgb multiscale {H}x{W} precision={precision}", flush=True)
+    pairs = [synth.noisy_pair(90 + i, H, W, 3, 25.0) for i in range(3)]
+    q_theta, t_s, t_c = 24, [0.03, 0.06], [0.25, 0.5]
+    K = q_theta * 9
+    st = O.GramStats.zeros(K, 3, 98)
+    g = M.Gram(K, 3, 3, 3)
+    sel = M.Level(q_theta, t_s, t_c, 3, 3, torch.zeros((K, 3, 98), device="cuda"), 3)
+    for z, u in pairs:
+        z64, u64 = z.astype(np.float64), u.astype(np.float64)
+        pz = O.build_pyramid(z64, 2, storage=np.float32)
+        s = O.select(z64, q_theta, t_s, t_c)
+        O.accumulate_level(st, s, O.to_filter_space(z64), O.to_filter_space(u64), 3, 3, O.to_filter_space(pz[1]))
+        zc = M.pyramid_build(_dev(z), 1)[0]
+        M.train_accumulate(g, _dev(z), _dev(u), sel, u_coarse=zc, coarse_color=M.RGB, precision=precision)
+    assert int(st.n.sum()) == 3 * H * W
+    worst = _check_gram(g, st, tol)
+    print(f"  worst ratio {worst:.3g}")
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 2e-5), (1, 2e-4)])
 def test_gram_cross_channel_147(precision, tol):
     """Cross-channel layout (x = the three channels' 7x7 patches, D = 147, three right-hand sides)
     against the oracle's cross-channel normal equations; then the solved filters' output-space error
