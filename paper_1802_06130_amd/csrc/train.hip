@@ -472,20 +472,32 @@ __global__ __launch_bounds__(1024) void k_work_items(const int32_t* off, int K, 
 // float32 YCbCr (or grey) planes of an RGB / grey image for the sample gathers, with a margin of
 // kPad pixels on every side holding the clamped (replicated) border: padded element (y, x),
 // -kPad <= y < h + kPad and -kPad <= x < w + kPad, is at out[(y + kPad) o_row + x + kPad].
-__global__ void k_to_planes(ImageArg in, int32_t dtype, int32_t rgb_to_ycc, int32_t C, float* out, int64_t o_row,
-                            int64_t o_plane) {
+struct PlaneJob {
+    ImageArg in;
+    int32_t dtype, rgb_to_ycc, C;
+    float* out;
+    int64_t o_row, o_plane;
+};
+struct PlaneJobs {
+    PlaneJob job[3];
+};
+
+// blockIdx.z picks the image: z^l, u^l and (when given) u^{l+1} in one launch
+__global__ void k_to_planes(PlaneJobs jobs) {
+    const PlaneJob& j = jobs.job[blockIdx.z];
+    const ImageArg& in = j.in;
     const int xp = blockIdx.x * blockDim.x + threadIdx.x;
     const int yp = blockIdx.y;
     if (xp >= in.w + 2 * kPad || yp >= in.h + 2 * kPad) return;
     const int x = clampi(xp - kPad, 0, in.w - 1), y = clampi(yp - kPad, 0, in.h - 1);
     const int64_t off = (int64_t)y * in.row + x;
     float v[3] = {0, 0, 0};
-    for (int c = 0; c < C; ++c) {
-        v[c] = dtype == MDN_F16 ? __half2float(static_cast<const __half*>(in.data)[off + c * in.plane])
-                                : static_cast<const float*>(in.data)[off + c * in.plane];
+    for (int c = 0; c < j.C; ++c) {
+        v[c] = j.dtype == MDN_F16 ? __half2float(static_cast<const __half*>(in.data)[off + c * in.plane])
+                                  : static_cast<const float*>(in.data)[off + c * in.plane];
     }
-    if (C == 3 && rgb_to_ycc) Ycc::from_rgb(v[0], v[1], v[2], v[0], v[1], v[2]);
-    for (int c = 0; c < C; ++c) out[c * o_plane + (int64_t)yp * o_row + xp] = v[c];
+    if (j.C == 3 && j.rgb_to_ycc) Ycc::from_rgb(v[0], v[1], v[2], v[0], v[1], v[2]);
+    for (int c = 0; c < j.C; ++c) j.out[c * j.o_plane + (int64_t)yp * j.o_row + xp] = v[c];
 }
 
 // ---------------------------------------------------------------- bucket grouping
@@ -930,10 +942,22 @@ size_t train_ws_bytes(const mdn_gram& g, int w, int h) {
 }
 
 // padded float32 gather planes of im (row pitch and plane pitch of the padded planes)
-mdn_status launch_to_planes(const mdn_image& im, float* out, int64_t row, int64_t plane, hipStream_t st) {
-    ImageArg a{im.data, im.row_pitch, im.plane_pitch, im.width, im.height};
-    dim3 grid((im.width + 2 * kPad + 255) / 256, im.height + 2 * kPad);
-    k_to_planes<<<grid, 256, 0, st>>>(a, im.dtype, im.color == MDN_RGB, im.channels, out, row, plane);
+// padded float32 gather planes of up to three images in one launch (row and plane pitches of the
+// padded planes per image)
+static mdn_status launch_to_planes(const mdn_image* const* ims, float* const* outs, const int64_t* rows, const int64_t* planes,
+                            int n, hipStream_t st) {
+    PlaneJobs jobs;
+    memset(&jobs, 0, sizeof(jobs));
+    int wmax = 0, hmax = 0;
+    for (int i = 0; i < n; ++i) {
+        const mdn_image& im = *ims[i];
+        jobs.job[i] = PlaneJob{ImageArg{im.data, im.row_pitch, im.plane_pitch, im.width, im.height}, im.dtype,
+                               im.color == MDN_RGB, im.channels, outs[i], rows[i], planes[i]};
+        wmax = im.width > wmax ? im.width : wmax;
+        hmax = im.height > hmax ? im.height : hmax;
+    }
+    dim3 grid((wmax + 2 * kPad + 255) / 256, hmax + 2 * kPad, n);
+    k_to_planes<<<grid, 256, 0, st>>>(jobs);
     return check_launch("to_planes");
 }
 
@@ -966,9 +990,13 @@ mdn_status train_accumulate(const mdn_gram& g, const mdn_image& z, const mdn_ima
     p += al(group_ws_bytes((int64_t)W * H, g.K));
     float* part = reinterpret_cast<float*>(p);
     mdn_status s;
-    if ((s = launch_to_planes(z, fine, Wp, (int64_t)Wp * Hp, st))) return s;
-    if ((s = launch_to_planes(target, tgt, Wp, (int64_t)Wp * Hp, st))) return s;
-    if (uc && (s = launch_to_planes(*uc, coarse, Wcp, (int64_t)Wcp * Hcp, st))) return s;
+    {
+        const mdn_image* ims[3] = {&z, &target, uc};
+        float* outs[3] = {fine, tgt, coarse};
+        const int64_t rows[3] = {Wp, Wp, Wcp};
+        const int64_t planes[3] = {(int64_t)Wp * Hp, (int64_t)Wp * Hp, (int64_t)Wcp * Hcp};
+        if ((s = launch_to_planes(ims, outs, rows, planes, uc ? 3 : 2, st))) return s;
+    }
     if ((s = launch_select_apply(z, uc, nullptr, W, smap, sel, nullptr, st))) return s;
     const int64_t npx = (int64_t)W * H;
     if ((s = group_by_bucket(smap, wide, npx, g.K, gws, idx, off, st))) return s;
