@@ -872,10 +872,10 @@ mdn_status gram_zero(const mdn_gram& g, hipStream_t st) {
     return check_launch("gram_zero");
 }
 
-// Slices of the bucket grouping: P pixels each (a power of two, at least 1024), enough pixels per
+// Slices of the bucket grouping: P pixels each (a power of two, at least 256), enough pixels per
 // slice that the K x B counts stay within 2^20 entries (1024 scan blocks).
 static void group_shape(int64_t n, int K, int* B, int* P) {
-    int64_t p = 1024;
+    int64_t p = 256;
     while ((int64_t)K * ((n + p - 1) / p) > (1 << 20)) p *= 2;
     *P = (int)p;
     *B = (int)((n + p - 1) / p);
