@@ -12,15 +12,15 @@
 // of S 64-sample chunks (the last one shorter), so that every workgroup has about the same work
 // however the samples fall into buckets; S is chosen for about two items per resident workgroup
 // (fewer, longer items write fewer partial sums; more, shorter ones balance better). The items
-// are numbered bucket by bucket and a workgroup finds its bucket by binary search. A workgroup gathers 64 samples at a time into LDS as a feature-major
-// matrix X^T (regression taps followed by the target value(s), zero padded to a multiple of 32;
-// the gathers of the next chunk are in flight while the current one is multiplied). The planes
-// are float32 copies with a replicated margin of kPad pixels, so every tap row of a sample is
-// consecutive floats of one plane row: a wave takes whole tap rows, one sample per lane, each
-// row one contiguous load,
-// and accumulates the upper-triangle 32x32 tiles of X^T X on MFMA with FP32 accumulators. The
-// target value rides along as an extra feature, so the same tiles yield G = sum x x^T,
-// b = sum x y and yy = sum y^2. Two products are offered:
+// are numbered bucket by bucket and a workgroup finds its bucket by binary search.
+// A workgroup gathers 64 samples at a time into LDS as a feature-major matrix X^T (regression
+// taps followed by the target value(s), zero padded to a multiple of 32; the gathers of the next
+// chunk are in flight while the current one is multiplied). The planes are float32 copies with a
+// replicated margin of kPad pixels, so every tap row of a sample is consecutive floats of one
+// plane row: a wave takes whole tap rows, one sample per lane, each row one contiguous load. The
+// upper-triangle 32x32 tiles of X^T X accumulate on MFMA with FP32 accumulators; the target value
+// rides along as an extra feature, so the same tiles yield G = sum x x^T, b = sum x y and
+// yy = sum y^2. Two products are offered:
 //   MDN_GRAM_F32    : v_mfma_f32_32x32x2_f32 - exact FP32 products, FP32 accumulation;
 //   MDN_GRAM_BF16X3 : v_mfma_f32_32x32x16_bf16 on a hi/lo split x = hi + lo (hi = bf16(x),
 //                     lo = bf16(x - hi)); x y ~ hi_x hi_y + hi_x lo_y + lo_x hi_y.
