@@ -97,11 +97,12 @@ def _gap_thresholds(f, q):
 
 
 @pytest.mark.parametrize("q_theta,q,phases,H,W,n", [(64, 16, 1, 96, 96, 3), (64, 16, 4, 96, 96, 3),
-                                                     (16, 16, 1, 512, 768, 1)])
+                                                     (16, 16, 1, 512, 768, 1), (2, 1, 1, 256, 320, 2)])
 def test_gram_with_many_buckets(q_theta, q, phases, H, W, n):
     """The bucket grouping at its limits: 16384 buckets and 65536 with phases (the largest K, 16-bit
-    keys, running positions in global memory), and 4096 buckets over 393216 pixels (slices of 2048
-    pixels, 768 scan blocks, positions in LDS): the normal equations still match bucket by bucket."""
+    keys, running positions in global memory), 4096 buckets over 393216 pixels (slices of 512 pixels,
+    768 scan blocks, positions in LDS), and 2 buckets (one-bit keys; runs of about 80000 samples, so
+    each bucket's partial sums span many work items): the normal equations match bucket by bucket."""
     import paper_1802_06130_amd as M
     torch = _torch()
     K = q_theta * q * q * phases
@@ -114,7 +115,7 @@ def test_gram_with_many_buckets(q_theta, q, phases, H, W, n):
     for z, u in pairs:
         s = O.select(z.astype(np.float64), q_theta, t_s, t_c, phases=phases)
         O.accumulate_level(st, s, O.to_filter_space(z), O.to_filter_space(u), 1)
-    assert np.count_nonzero(st.n) > 1000
+    assert np.count_nonzero(st.n) > min(1000, K - 1)
     g = M.Gram(K, 1, 1)
     sel = M.Level(q_theta, t_s, t_c, 1, None, torch.zeros((K, 1, 9), device="cuda"), 1, phases=phases)
     for z, u in pairs:
