@@ -43,3 +43,42 @@ def test_noalloc_refuses_images_above_the_scratch():
     with pytest.raises(M.MdnError) as e:
         M.denoise_noalloc(z, gb, storage=M.F32)
     assert e.value.status == M.MDN_ENOMEM
+
+
+@pytest.mark.parametrize("storage", ["f16", "f32"])
+def test_noalloc_under_graph_capture(storage):
+    """The callers it is for: the cascade captured into a HIP graph (it allocates nothing, so the
+    capture holds only kernel launches) and replayed three times, with eager calls of the same entry
+    point between the replays; every replay and every eager call equals mdn_denoise bit for bit."""
+    import torch
+    import paper_1802_06130_amd as M
+    f16 = storage == "f16"
+    print(f"noalloc under graph capture, {storage} storage", flush=True)
+    bank = trained_bank_multiscale(levels=3)
+    gb = gpu_bank(bank, 3, coeff_dtype=torch.float16 if f16 else torch.float32)
+    code = M.F16 if f16 else M.F32
+    dt = np.float16 if f16 else np.float32
+    z = torch.from_numpy(synth.noisy_pair(6200, 333, 517, 3, 25, dtype=dt)[0]).cuda()
+    z2 = torch.from_numpy(synth.noisy_pair(6201, 200, 150, 3, 25, dtype=dt)[0]).cuda()
+    want = M.denoise(z, gb, storage=code)
+    want2 = M.denoise(z2, gb, storage=code)
+    out = torch.empty_like(z)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        M.denoise_noalloc(z, gb, storage=code, out=out)      # first use of the scratch, outside capture
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        M.denoise_noalloc(z, gb, storage=code, out=out)
+    out2 = torch.empty_like(z2)
+    for r in range(3):
+        out.fill_(float("nan"))
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, want), f"replay {r + 1} differs from mdn_denoise"
+        M.denoise_noalloc(z2, gb, storage=code, out=out2)     # eager, smaller, on the same scratch
+        torch.cuda.synchronize()
+        assert torch.equal(out2, want2), f"eager call after replay {r + 1} differs from mdn_denoise"
+    del graph
