@@ -31,3 +31,29 @@ def test_gram_mfma_flop_counts_the_upper_triangle_tiles():
     assert bench.gram_mfma_flop(98, 3, 1) == 2.0 * 10 * 32 * 32 * 3
     assert bench.gram_mfma_flop(25, 1, 7) == 2.0 * 1 * 32 * 32 * 7
     assert bench.gram_mfma_flop(147, 1, 1) == 2.0 * 15 * 32 * 32
+
+
+def test_spread_reports_the_percentiles_of_the_timings():
+    sys.path.insert(0, ROOT)
+    import bench
+    d = bench.spread(list(range(101)), "t")
+    assert d == {"p10": 10.0, "p50": 50.0, "p90": 90.0, "p99": 99.0, "what": "t"}
+
+
+def test_quality_items_are_8bit_noisy_views_of_one_scene():
+    """A quality-run item: the clean scene in [0, 1] and one noisy observation per noise level, each a
+    multiple of 1/255 in [0, 1] (to float32 rounding) whose error against the scene has about the level's deviation."""
+    sys.path.insert(0, ROOT)
+    import numpy as np
+    import bench
+    u, zs = bench._make_quality_item((8001, 321, 481))
+    assert u.shape == (3, 321, 481) and float(u.min()) >= 0.0 and float(u.max()) <= 1.0
+    assert len(zs) == len(bench.QUALITY_SIGMAS)
+    for g, z in zip(bench.QUALITY_SIGMAS, zs):
+        q = z.astype(np.float64) * 255.0
+        assert np.abs(q - np.round(q)).max() < 1e-4 and q.min() >= 0 and q.max() <= 255   # float32 k / 255
+        inner = (u > 0.25) & (u < 0.75)          # away from the clamp
+        sd = float(np.std((z.astype(np.float64) - u)[inner])) * 255.0
+        assert abs(sd - g) < 0.05 * g + 0.5, (g, sd)
+    noisy_psnr = [bench._psnr(z, u) for z in zs]
+    assert noisy_psnr[0] > noisy_psnr[1] > noisy_psnr[2]
