@@ -619,8 +619,9 @@ def measured_traffic():
 def pmc_probe():
     """For hardware-counter runs: one copy kernel of known size (512 MiB read + written), then the
     bench's batch of images through the batched form (autotuned strip heights), its launches once
-    more one at a time: the last nine dispatches are the pyramid (levels 0 -> 1 -> 2 -> 3), then
-    selection and filtering of levels 2, 1 and 0. The bank has random coefficients."""
+    more one at a time: the last six dispatches are the pyramid steps with their levels' selection
+    passes (levels 0 -> 1 -> 2 -> 3, one launch each), then the filtering of levels 2, 1 and 0. The
+    bank has random coefficients."""
     sizes, imgs, _ = make_inputs(N_IMAGES, np.float16)     # before the GPU is touched (worker pool)
     import torch
     import paper_1802_06130_amd as M
@@ -965,7 +966,7 @@ def main():
                          "algorithmic_flop_per_px": FLOP_PER_PX,
                          "hbm_frac": round(hbm / HBM_PEAK_GBS, 4)},
                      "kernel_us_per_level": [[round(t, 1) for t in lv] for lv in ktimes],
-                     "kernel_us_order": "per level 0, 1, 2: pyramid (level l -> l+1), selection, filtering",
+                     "kernel_us_order": "per level 0, 1, 2: pyramid step (level l -> l+1; where the level has one column-walk bank its selection pass runs in the same launch and the selection entry is 0), selection, filtering",
                      "per_image_launch": {"mean_px": round(img_px), "avg_launch_us": round(img_dur * 1e6, 2),
                                           "TFLOP/s": round(FLOP_PER_PX * img_px / img_dur / 1e12, 2),
                                           "what": "the same kernel launched per image on the first 16 images"}},

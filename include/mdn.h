@@ -314,8 +314,10 @@ mdn_status mdn_plan_autotune(mdn_plan* plan, const mdn_image* in, const mdn_imag
  * plan stream between two HIP events, `reps` times (1..1000); us_out (host float[3*levels]) receives
  * the mean microseconds of the pyramid, selection and filtering launches of each level (index
  * 3 l + k, all banks together; a level on the tiled kernel reports its launches as filtering and
- * about nothing for selection). The outputs are written as by mdn_denoise_batch. Synchronises the
- * plan's stream. */
+ * about nothing for selection). Where a level's selection pass runs in the launch of its pyramid
+ * step (a level with a single column-walk bank), that launch's time is the pyramid entry and the
+ * selection entry is 0. The outputs are written as by mdn_denoise_batch. Synchronises the plan's
+ * stream. */
 mdn_status mdn_plan_kernel_times(mdn_plan* plan, const mdn_image* in, const mdn_image* out, const int32_t* bank,
                                  int32_t n, int32_t reps, float* us_out, void* stream);
 
@@ -329,7 +331,7 @@ mdn_status mdn_denoise_batch(mdn_plan* plan, const mdn_image* in, const mdn_imag
  * Serving loop (host code above the calls of this header): requests of any sizes arrive over
  * time, each naming one of several device-resident banks (one per noise level, which is taken
  * as known, Section 5). A request is admitted when a slot is free and its device footprint
- * (input, output, pyramid levels, selector map) fits the memory budget, first come first served
+ * (input, output, pyramid levels, selector maps) fits the memory budget, first come first served
  * with no overtaking. Its input is copied to the device on a copy stream; it then joins the next
  * scheduling tick. A tick advances every active request by up to stages_per_tick cascade stages
  * (pyramid levels 0..L-1, then selection and filtering of levels L-1..0, Section 4) with one
@@ -423,7 +425,7 @@ mdn_status mdn_server_replay(mdn_server* server, const mdn_request* reqs, const 
 mdn_status mdn_server_stats(mdn_server* server, mdn_server_counters* out);
 mdn_status mdn_server_now(mdn_server* server, double* seconds);
 /* Device bytes the request would hold while admitted: input and output (each rounded up to 256
- * bytes) plus its pyramid levels (rows padded to 64 elements) and selector map. */
+ * bytes) plus its pyramid levels (rows padded to 64 elements) and one selector map per level. */
 mdn_status mdn_server_footprint(mdn_server* server, const mdn_request* req, uint64_t* bytes);
 
 /* MDN_EXEC_FAKE only: move the virtual clock forward to t, and force failures or delays on the

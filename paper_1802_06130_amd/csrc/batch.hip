@@ -13,6 +13,11 @@
 
 #include "walk_types.h"
 
+// 0: the pyramid steps and selection passes of a batch always run as launches of their own
+#ifndef MDN_FUSE_PYR_SEL
+#define MDN_FUSE_PYR_SEL 1
+#endif
+
 using namespace mdn;
 
 namespace {
@@ -134,11 +139,23 @@ mdn_status ensure_tables(mdn_plan* p, size_t need) {
 
 namespace mdn {
 
-size_t batch_image_ws(int w, int h, int L, int storage) { return image_ws(w, h, L, storage) + al256((size_t)w * h); }
+// the selector maps of levels 0 .. L-1, one each: a level's selection may run long before its
+// filtering (beside a pyramid step), so the levels cannot share one map
+size_t batch_maps_bytes(int w, int h, int L) {
+    size_t b = 0;
+    for (int l = 0; l < L; ++l) {
+        b += al256((size_t)w * h);
+        w = (w + 1) / 2;
+        h = (h + 1) / 2;
+    }
+    return b;
+}
+
+size_t batch_image_ws(int w, int h, int L, int storage) { return image_ws(w, h, L, storage) + batch_maps_bytes(w, h, L); }
 
 // Per-level descriptors of one image's cascade, each with strip_begin = 0: d2[l] makes z^{l+1}
 // from z^l, sel[l] and walk[l] run level l (walk[0] writes `out`). ws (batch_image_ws bytes,
-// 256-aligned) holds z^1..z^L, u^1..u^{L-1} and the selector map, which every level reuses.
+// 256-aligned) holds z^1..z^L, u^1..u^{L-1} and the selector maps of levels 0..L-1.
 void describe_cascade(const mdn_image& in, const mdn_image& out, void* ws, int L, int storage, const int (*rows)[3],
                       int ncu, D2Image* d2, SelImage* sel, WalkImage* walk, TileImage* tile) {
     mdn_image zl[kMaxLevels + 1], ul[kMaxLevels + 1];
@@ -157,10 +174,11 @@ void describe_cascade(const mdn_image& in, const mdn_image& out, void* ws, int L
             w += b;
         }
     }
-    uint8_t* smap = reinterpret_cast<uint8_t*>(w);
     for (int l = 0; l < L; ++l) {
         const mdn_image& a = zl[l];
         const mdn_image& o = zl[l + 1];
+        uint8_t* smap = reinterpret_cast<uint8_t*>(w);
+        w += al256((size_t)a.width * a.height);
         D2Image& d = d2[l];
         memset(&d, 0, sizeof(d));
         d.in = a.data;
@@ -420,9 +438,69 @@ mdn_status prepare(mdn_plan* p, const mdn_image* in, const mdn_image* out, const
 mdn_status run_d2(mdn_plan* p, int l) { return run_group(p, 0, l); }
 mdn_status run_sel(mdn_plan* p, int l) { return run_group(p, 1, l); }
 mdn_status run_walk(mdn_plan* p, int l) { return run_group(p, 2, l); }
+// The selection item that runs in the launch of pyramid item `d2` (same level): the level's only
+// selection pass, when its bank allows it; items.size() when none does.
+size_t fused_selection(const std::vector<BatchItem>& items, const BatchItem& d2) {
+    size_t sel = items.size();
+    int nsel = 0;
+    for (size_t j = 0; j < items.size(); ++j)
+        if (items[j].kind == 1 && items[j].level == d2.level) {
+            sel = j;
+            ++nsel;
+        }
+    return (MDN_FUSE_PYR_SEL && nsel == 1 && pyr_sel_fusable(items[sel].sel)) ? sel : items.size();
+}
+mdn_status launch_fused(const BatchLaunch& bl, const BatchItem& d2, const BatchItem& si, hipStream_t st) {
+    D2Args d = d2.d2;
+    d.imgs = reinterpret_cast<const D2Image*>(bl.tab_dev + d2.tab_off);
+    SelWalkArgs a = si.sel;
+    a.imgs = reinterpret_cast<const SelImage*>(bl.tab_dev + si.tab_off);
+    return launch_pyr_sel_args(d, a, d2.z_dtype, bl.storage, st);
+}
+// The pyramid step of level l, with the level's selection pass in the same launch where possible;
+// *fused tells whether it was.
+mdn_status run_d2_fused(mdn_plan* p, int l, bool* fused) {
+    const std::vector<BatchItem>& items = p->bl.items;
+    *fused = false;
+    for (const BatchItem& it : items) {
+        if (it.kind != 0 || it.level != l) continue;
+        const size_t sel = fused_selection(items, it);
+        mdn_status e;
+        if (sel < items.size()) {
+            e = launch_fused(p->bl, it, items[sel], p->stream);
+            *fused = true;
+        } else {
+            e = launch_item(p->bl, it, p->stream);
+        }
+        if (e) return e;
+    }
+    return MDN_OK;
+}
+
+// The batch's launches: the pyramid steps first, each together with its level's selection pass in
+// one launch where the level has exactly one selection pass that allows it (one column-walk bank
+// over the images); then, from the coarsest level down, the remaining selection passes and the
+// filtering launches.
 mdn_status launch_all(mdn_plan* p) {
-    for (const BatchItem& it : p->bl.items) {
-        mdn_status e = launch_item(p->bl, it, p->stream);
+    const std::vector<BatchItem>& items = p->bl.items;
+    std::vector<char> done(items.size(), 0);
+    for (size_t i = 0; i < items.size(); ++i) {
+        const BatchItem& it = items[i];
+        if (it.kind != 0) continue;
+        done[i] = 1;
+        const size_t sel = fused_selection(items, it);
+        mdn_status e;
+        if (sel < items.size()) {
+            e = launch_fused(p->bl, it, items[sel], p->stream);
+            done[sel] = 1;
+        } else {
+            e = launch_item(p->bl, it, p->stream);
+        }
+        if (e) return e;
+    }
+    for (size_t i = 0; i < items.size(); ++i) {
+        if (done[i]) continue;
+        mdn_status e = launch_item(p->bl, items[i], p->stream);
         if (e) return e;
     }
     return MDN_OK;
@@ -684,16 +762,27 @@ mdn_status mdn_plan_kernel_times(mdn_plan* p, const mdn_image* in, const mdn_ima
         if (hipEventSynchronize(ev[i + 1]) != hipSuccess) return fail(MDN_EDEVICE, "plan: event wait failed");
         return MDN_OK;
     };
+    std::vector<char> fused(L, 0);
     for (int r = 0; r < reps && !st; ++r) {
-        for (int l = 0; l < L && !st; ++l) st = timed(slot(r, l, 0), [&] { return run_d2(p, l); });
+        for (int l = 0; l < L && !st; ++l)
+            st = timed(slot(r, l, 0), [&] {
+                bool f = false;
+                const mdn_status e = run_d2_fused(p, l, &f);
+                fused[l] = f;
+                return e;
+            });
         for (int l = L - 1; l >= 0 && !st; --l) {
-            st = timed(slot(r, l, 1), [&] { return run_sel(p, l); });
+            if (!fused[l]) st = timed(slot(r, l, 1), [&] { return run_sel(p, l); });
             if (!st) st = timed(slot(r, l, 2), [&] { return run_walk(p, l); });
         }
     }
     if (!st && hipEventSynchronize(ev.back()) != hipSuccess) st = fail(MDN_EDEVICE, "plan: event wait failed");
     for (int l = 0; l < L && !st; ++l)
         for (int k = 0; k < 3; ++k) {
+            if (k == 1 && fused[l]) {
+                us_out[3 * l + k] = 0.0f;       // the selection ran in the pyramid step's launch
+                continue;
+            }
             double sum = 0.0;
             for (int r = 0; r < reps; ++r) {
                 float ms = 0.0f;

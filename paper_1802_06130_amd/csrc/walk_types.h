@@ -17,6 +17,20 @@ constexpr int kD2LanesOut = 60;     // pyramid: output columns per wave (2-colum
 #endif
 constexpr int kWalkWaves = MDN_WALK_WAVES;   // filtering: waves per workgroup (one workgroup per CU)
 
+// A value every lane holds alike, moved to scalar registers word by word. A strip's image descriptor
+// is read either from the kernel arguments or from the launch's table; the compiler may read both
+// through one generic pointer, which would leave the descriptor and all addressing derived from it
+// in vector registers.
+template <typename T> __device__ __forceinline__ T wave_uniform(const T& v) {
+    static_assert(sizeof(T) % 4 == 0, "whole words");
+    T r;
+    const uint32_t* s = reinterpret_cast<const uint32_t*>(&v);
+    uint32_t* d = reinterpret_cast<uint32_t*>(&r);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) d[i] = (uint32_t)__builtin_amdgcn_readfirstlane((int)s[i]);
+    return r;
+}
+
 struct WalkImage {
     const void* z;          // RGB input of the level
     const void* uc;         // coarser output (YCbCr, or RGB at the coarsest level)
@@ -92,6 +106,10 @@ mdn_status init_walk_kernels();
 mdn_status launch_walk_args(const WalkArgs& a, int z_dtype, int uc_dtype, int o_dtype, hipStream_t st);
 mdn_status launch_select_args(const SelWalkArgs& a, int channels, int z_dtype, hipStream_t st);
 mdn_status launch_down2_args(const D2Args& a, int channels, int in_dtype, int out_dtype, hipStream_t st);
+// a pyramid step and the selection pass of the same level (RGB, uint8 map, colour selector) in one
+// launch; pyr_sel_fusable tells whether the selection's bank allows it
+bool pyr_sel_fusable(const SelWalkArgs& s);
+mdn_status launch_pyr_sel_args(const D2Args& d, const SelWalkArgs& s, int level_dtype, int next_dtype, hipStream_t st);
 
 
 // ---------------------------------------------------------------- batched cascade

@@ -95,8 +95,9 @@ def test_batch_rejects_bad_inputs():
 
 def test_kernel_times_runs_the_same_launches():
     """mdn_plan_kernel_times runs the batch's launches one at a time between events: positive times for
-    every kernel and level, outputs equal to the batched form's bit for bit; before and after a graph
-    replay of the same batch."""
+    every pyramid step and filtering launch, the selection entry 0 on every level (this single
+    column-walk bank runs each level's selection in its pyramid step's launch), outputs equal to the
+    batched form's bit for bit; before and after a graph replay of the same batch."""
     import torch
     import paper_1802_06130_amd as M
     gb, zs = _setup()
@@ -105,7 +106,7 @@ def test_kernel_times_runs_the_same_launches():
     outs = [torch.full_like(z, -1.0) for z in zs]
     kt = plan.kernel_times(zs, outs, reps=2)
     torch.cuda.synchronize()
-    assert len(kt) == len(gb.levels) and all(t > 0.0 for lv in kt for t in lv)
+    assert len(kt) == len(gb.levels) and all(lv[0] > 0.0 and lv[1] == 0.0 and lv[2] > 0.0 for lv in kt)
     for o, w in zip(outs, want):
         assert np.array_equal(o.cpu().numpy(), w)
     again = [o.cpu().numpy() for o in plan.denoise_batch(zs, use_graph=True)]

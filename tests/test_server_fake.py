@@ -87,7 +87,10 @@ def test_footprint_matches_layout():
         w, h = (w + 1) // 2, (h + 1) // 2
         lvl = al((w + 63) // 64 * 64 * h * 3 * 2)
         want += lvl * (2 if l < LEVELS else 1)
-    want += al(1001 * 777)
+    w, h = 1001, 777
+    for l in range(LEVELS):                 # one uint8 selector map per trained level
+        want += al(w * h)
+        w, h = (w + 1) // 2, (h + 1) // 2
     assert fp == want
 
 
