@@ -274,7 +274,13 @@ mdn_status mdn_denoise_workspace_size(int32_t width, int32_t height, int32_t cha
         total += image_bytes(w, h, channels, storage);                 // z^l
         if (l < levels) total += image_bytes(w, h, channels, storage); // u^l
     }
-    total += align256((size_t)width * (size_t)height);                  // selector map (largest level)
+    w = width;
+    h = height;
+    for (int l = 0; l < levels; ++l) {                                   // selector map of level l
+        total += align256((size_t)w * (size_t)h);
+        w = half_up(w);
+        h = half_up(h);
+    }
     *bytes = total;
     return MDN_OK;
 }
@@ -325,19 +331,37 @@ mdn_status mdn_denoise(const mdn_image* in, const mdn_bank* bank, int32_t storag
             p += image_bytes(w, h, C, storage);
         }
     }
-    uint8_t* smap = reinterpret_cast<uint8_t*>(p);
     zl[0] = *in;
-    for (int l = 1; l <= L; ++l)
-        if ((st = launch_down2(zl[l - 1], zl[l], s))) return st;
+    // uint8 selector maps, one per level: they serve the column walk and the LDS-bank kernel
+    uint8_t* smap[17];
+    for (int l = 0; l < L; ++l) {
+        smap[l] = reinterpret_cast<uint8_t*>(p);
+        p += align256((size_t)zl[l].width * (size_t)zl[l].height);
+    }
+    auto uses_map = [&](int l) {
+        const mdn_level& lv = bank->level[l];
+        return (lv.coeff_dtype == MDN_F16 && walk_supported(lv, C)) || (!wide_selector(lv) && apply_lds_supported(lv, C));
+    };
+    // pyramid steps; a level whose filtering reads a map has its selection pass in the same launch
+    bool selected[17] = {};
+    for (int l = 0; l < L; ++l) {
+        const mdn_level& lv = bank->level[l];
+        if (uses_map(l) && pyr_sel_fits(lv, C)) {
+            st = launch_pyr_sel(zl[l], zl[l + 1], lv, smap[l], zl[l].width, s);
+            selected[l] = true;
+        } else {
+            st = launch_down2(zl[l], zl[l + 1], s);
+        }
+        if (st) return st;
+    }
     // u^L = z^L (read as RGB and converted by the level L-1 step)
     const mdn_image* coarse = &zl[L];
     for (int l = L - 1; l >= 0; --l) {
         const mdn_image* dst = l == 0 ? out : &ul[l];
-        // the map buffer holds uint8 maps: it serves the column walk and the LDS-bank kernel
         const mdn_level& lv = bank->level[l];
-        const bool walk = lv.coeff_dtype == MDN_F16 && walk_supported(lv, C);
-        const bool map = walk || (!wide_selector(lv) && apply_lds_supported(lv, C));
-        if ((st = launch_select_apply(zl[l], coarse, nullptr, zl[l].width, map ? smap : nullptr, lv, dst, s)))
+        const bool map = uses_map(l);
+        if ((st = launch_select_apply(zl[l], coarse, selected[l] ? smap[l] : nullptr, zl[l].width,
+                                      map && !selected[l] ? smap[l] : nullptr, lv, dst, s)))
             return st;
         coarse = dst;
     }

@@ -47,9 +47,7 @@ mdn_status launch_down2_args(const D2Args& a, int C, int in_dtype, int out_dtype
     return fail(MDN_EINVAL, "down2: unsupported dtype pair");
 }
 
-mdn_status launch_down2_walk(const mdn_image& in, const mdn_image& out, hipStream_t st) {
-    if (out.width == 0 || out.height == 0) return MDN_OK;
-    D2Args a;
+void fill_down2_single(const mdn_image& in, const mdn_image& out, D2Args& a) {
     memset(&a, 0, sizeof(a));
     D2Image& im = a.single;
     im.in = in.data;
@@ -66,6 +64,12 @@ mdn_status launch_down2_walk(const mdn_image& in, const mdn_image& out, hipStrea
     im.rows = down2_rows(out.width, out.height, device_cus());
     a.n_imgs = 1;
     a.n_strips = im.nsx * ((out.height + im.rows - 1) / im.rows);
+}
+
+mdn_status launch_down2_walk(const mdn_image& in, const mdn_image& out, hipStream_t st) {
+    if (out.width == 0 || out.height == 0) return MDN_OK;
+    D2Args a;
+    fill_down2_single(in, out, a);
     return launch_down2_args(a, in.channels, in.dtype, out.dtype, st);
 }
 

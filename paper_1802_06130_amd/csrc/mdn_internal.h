@@ -140,6 +140,11 @@ mdn_status launch_apply_lds(const mdn_image& z, const mdn_image& uc, const void*
 mdn_status launch_walk(const mdn_image& z, const mdn_image& uc, const mdn_level& lvl, const mdn_image& out,
                        const uint8_t* s_in, uint8_t* s_buf, int64_t s_pitch, hipStream_t st);
 mdn_status launch_select_walk(const mdn_image& z, const mdn_level& lvl, void* s, int64_t s_pitch, hipStream_t st);
+// The pyramid step z -> next and the selection pass of z (uint8 map s) in one launch; for RGB levels
+// with the colour selector, one phase and at most 256 buckets (pyr_sel_fits).
+bool pyr_sel_fits(const mdn_level& lvl, int channels);
+mdn_status launch_pyr_sel(const mdn_image& z, const mdn_image& next, const mdn_level& lvl, void* s, int64_t s_pitch,
+                          hipStream_t st);
 mdn_status launch_dihedral(const mdn_image& in, const mdn_image& out, int t, hipStream_t st);
 // su: select on the upsampled coarser output su instead of z (z then only gives the size)
 mdn_status launch_features(const mdn_image& z, int luma, const mdn_image* su, double* strength, double* coherence,

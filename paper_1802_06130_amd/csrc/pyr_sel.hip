@@ -74,4 +74,19 @@ mdn_status launch_pyr_sel_args(const D2Args& d, const SelWalkArgs& s, int level_
     return check_launch("pyr_sel");
 }
 
+bool pyr_sel_fits(const mdn_level& lvl, int channels) {
+    return channels == 3 && lvl.selector == MDN_SELECT_RGB && lvl.phases == 1 && level_buckets(lvl) <= 256;
+}
+
+mdn_status launch_pyr_sel(const mdn_image& z, const mdn_image& next, const mdn_level& lvl, void* s, int64_t s_pitch,
+                          hipStream_t st) {
+    if (!pyr_sel_fits(lvl, z.channels)) return fail(MDN_EINVAL, "pyramid and selection: level not supported");
+    if (z.width == 0 || z.height == 0) return MDN_OK;
+    D2Args d;
+    SelWalkArgs a;
+    fill_down2_single(z, next, d);
+    fill_select_single(z, lvl, s, s_pitch, a);
+    return launch_pyr_sel_args(d, a, z.dtype, next.dtype, st);
+}
+
 }  // namespace mdn

@@ -93,9 +93,7 @@ mdn_status launch_select_args(const SelWalkArgs& a, int channels, int z_dtype, h
     return check_launch("select_walk");
 }
 
-mdn_status launch_select_walk(const mdn_image& z, const mdn_level& lvl, void* s, int64_t s_pitch, hipStream_t st) {
-    if (z.width == 0 || z.height == 0) return MDN_OK;
-    SelWalkArgs a;
+void fill_select_single(const mdn_image& z, const mdn_level& lvl, void* s, int64_t s_pitch, SelWalkArgs& a) {
     memset(&a, 0, sizeof(a));
     SelImage& im = a.single;
     im.z = z.data;
@@ -113,6 +111,12 @@ mdn_status launch_select_walk(const mdn_image& z, const mdn_level& lvl, void* s,
     a.n_imgs = 1;
     a.n_strips = im.nsx * ((z.height + im.rows - 1) / im.rows);
     fill_sel_consts(lvl, a);
+}
+
+mdn_status launch_select_walk(const mdn_image& z, const mdn_level& lvl, void* s, int64_t s_pitch, hipStream_t st) {
+    if (z.width == 0 || z.height == 0) return MDN_OK;
+    SelWalkArgs a;
+    fill_select_single(z, lvl, s, s_pitch, a);
     return launch_select_args(a, z.channels, z.dtype, st);
 }
 

@@ -110,6 +110,9 @@ mdn_status launch_down2_args(const D2Args& a, int channels, int in_dtype, int ou
 // launch; pyr_sel_fusable tells whether the selection's bank allows it
 bool pyr_sel_fusable(const SelWalkArgs& s);
 mdn_status launch_pyr_sel_args(const D2Args& d, const SelWalkArgs& s, int level_dtype, int next_dtype, hipStream_t st);
+// single-image arguments of the pyramid step in -> out and of the selection pass of z
+void fill_down2_single(const mdn_image& in, const mdn_image& out, D2Args& a);
+void fill_select_single(const mdn_image& z, const mdn_level& lvl, void* s, int64_t s_pitch, SelWalkArgs& a);
 
 
 // ---------------------------------------------------------------- batched cascade

@@ -33,8 +33,9 @@ def test_version_string():
 
 def test_workspace_size_host_only():
     n = M.denoise_workspace_size(1024, 768, 3, 2, M.F32)
-    # z^1, u^1 (512 x 384) and z^2 (256 x 192), pitches rounded up to 64 elements, + selector map
-    want = 3 * 4 * (512 * 384 * 2 + 256 * 192) + 1024 * 768
+    # z^1, u^1 (512 x 384) and z^2 (256 x 192), pitches rounded up to 64 elements, + the uint8
+    # selector maps of levels 0 and 1
+    want = 3 * 4 * (512 * 384 * 2 + 256 * 192) + 1024 * 768 + 512 * 384
     assert n == want
     assert M.denoise_workspace_size(0, 0, 3, 3, M.F16) == 0
     with pytest.raises(M.MdnError):

@@ -192,3 +192,24 @@ def test_batch_with_a_bank_per_image(use_graph):
     with pytest.raises(M.MdnError):
         plan.denoise_batch(zs, outs, banks=[3] * len(zs))
     plan.close()
+
+
+def test_batch_float32_storage_equals_per_image():
+    """Float32 pyramid storage in the batched form (each level's pyramid step and selection pass in
+    one launch) with float32 images: every output equals the per-image call's bit for bit, eagerly
+    and from a graph. Float16 images need float16 storage in this form."""
+    import torch
+    import paper_1802_06130_amd as M
+    gb, zs = _setup(np.float32)
+    want = _plain(M, gb, zs, M.F32)
+    plan = M.Plan(gb, M.F32, max_images=16)
+    for use_graph in (False, True):
+        outs = plan.denoise_batch(zs, use_graph=use_graph)
+        torch.cuda.synchronize()
+        for i, (o, w) in enumerate(zip(outs, want)):
+            assert np.array_equal(o.cpu().numpy(), w), f"image {i} {SIZES[i]} differs (graph {use_graph})"
+    z16 = [z.half() for z in zs[:2]]
+    with pytest.raises(M.MdnError) as e:
+        plan.denoise_batch(z16)
+    assert e.value.status == M.MDN_ENOTSUP
+    plan.close()
