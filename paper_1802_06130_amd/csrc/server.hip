@@ -144,7 +144,11 @@ struct GroupKey {
     }
 };
 
-// Levels of a tiled bank level have no selection launch: the tiled kernel selects inline.
+// Levels of a tiled bank level have no selection launch: the tiled kernel selects inline. The
+// selection pass of a column-walk level runs in the launch of that level's pyramid step (kind 3,
+// one launch per bank and level), long before the level's filtering stage.
+bool selects_with_pyramid(const Bank& bk, int l) { return !bk.tiled[l] && pyr_sel_fusable(bk.selc[l]); }
+
 template <typename F>
 void for_each_group(const std::vector<Item>& items, int round, int storage, const Bank* banks, F&& f) {
     std::map<GroupKey, std::vector<const Item*>> g;
@@ -152,16 +156,21 @@ void for_each_group(const std::vector<Item>& items, int round, int storage, cons
         if (it.round != round) continue;
         const Request& r = *it.r;
         const int L = r.L;
+        const Bank& bk = banks[r.q.bank];
         if (it.stage < L) {
             const int l = it.stage;
-            g[{0, 0, 0, level_dtype(r, l, storage), storage}].push_back(&it);
+            if (selects_with_pyramid(bk, l)) g[{3, r.q.bank, l, level_dtype(r, l, storage), storage}].push_back(&it);
+            else g[{0, 0, 0, level_dtype(r, l, storage), storage}].push_back(&it);
         } else {
             const int l = 2 * L - 1 - it.stage;
-            if (!banks[r.q.bank].tiled[l]) g[{1, r.q.bank, l, level_dtype(r, l, storage), 0}].push_back(&it);
+            if (!bk.tiled[l] && !selects_with_pyramid(bk, l))
+                g[{1, r.q.bank, l, level_dtype(r, l, storage), 0}].push_back(&it);
             g[{2, r.q.bank, l, level_dtype(r, l, storage), level_dtype(r, l, storage)}].push_back(&it);
         }
     }
-    for (auto& kv : g) f(kv.first, kv.second);   // kind 0 (pyramid) < 1 (selection) < 2 (filtering)
+    // kind 0 (pyramid) < 1 (selection) < 2 (filtering) < 3 (pyramid with selection); the groups of a
+    // round hold different requests, so their order does not matter
+    for (auto& kv : g) f(kv.first, kv.second);
 }
 
 // ---------------------------------------------------------------- executors
@@ -270,11 +279,13 @@ public:
             size_t off;
             int n, strips;
             std::vector<Request*> reqs;
+            size_t off2 = 0;      // kind 3: the selection table after the pyramid table
+            int strips2 = 0;
         };
         std::vector<Launch> ls;
         for (int round = 0; round < rounds; ++round) {
             for_each_group(items, round, storage_, banks_, [&](const GroupKey& k, const std::vector<const Item*>& its) {
-                Launch L{k, used, (int)its.size(), 0, {}};
+                Launch L{k, used, (int)its.size(), 0, {}, 0, 0};
                 int begin = 0;
                 auto put = [&](const void* d, size_t n) {
                     if (used + n <= tab_cap_) memcpy(th + used, d, n);
@@ -282,8 +293,8 @@ public:
                 };
                 for (const Item* it : its) {
                     const Request& r = *it->r;
-                    const int l = k.kind == 0 ? it->stage : 2 * r.L - 1 - it->stage;
-                    if (k.kind == 0) {
+                    const int l = (k.kind == 0 || k.kind == 3) ? it->stage : 2 * r.L - 1 - it->stage;
+                    if (k.kind == 0 || k.kind == 3) {
                         D2Image d = r.d2[l];
                         d.strip_begin = begin;
                         begin += strips_of(d);
@@ -308,6 +319,18 @@ public:
                 }
                 L.strips = begin;
                 used = al256(used);
+                if (k.kind == 3) {
+                    L.off2 = used;
+                    begin = 0;
+                    for (const Item* it : its) {
+                        SelImage d = it->r->sel[it->stage];
+                        d.strip_begin = begin;
+                        begin += strips_of(d);
+                        put(&d, sizeof(d));
+                    }
+                    L.strips2 = begin;
+                    used = al256(used);
+                }
                 ls.push_back(std::move(L));
             });
         }
@@ -324,6 +347,17 @@ public:
                 a.n_imgs = L.n;
                 a.n_strips = L.strips;
                 st = launch_down2_args(a, 3, L.k.zd, storage_, comp_);
+            } else if (L.k.kind == 3) {
+                D2Args a;
+                memset(&a, 0, sizeof(a));
+                a.imgs = reinterpret_cast<const D2Image*>(td + L.off);
+                a.n_imgs = L.n;
+                a.n_strips = L.strips;
+                SelWalkArgs sa = bk.selc[L.k.level];
+                sa.imgs = reinterpret_cast<const SelImage*>(td + L.off2);
+                sa.n_imgs = L.n;
+                sa.n_strips = L.strips2;
+                st = launch_pyr_sel_args(a, sa, L.k.zd, storage_, comp_);
             } else if (L.k.kind == 1) {
                 SelWalkArgs a = bk.selc[L.k.level];
                 a.imgs = reinterpret_cast<const SelImage*>(td + L.off);

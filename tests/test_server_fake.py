@@ -49,10 +49,10 @@ def _cascade_time(w, h, levels=LEVELS, stages_per_tick=1):
         px.append(w * h)
         w, h = (w + 1) // 2, (h + 1) // 2
     t = 0.0
-    for l in range(levels):                          # pyramid stages, one launch each
+    for l in range(levels):                          # pyramid stages with the level's selection, one launch each
         t += LAUNCH_US * 1e-6 + 0.075 * px[l] / (GPX * 1e9)
-    for l in range(levels - 1, -1, -1):              # selection + filtering, two launches
-        t += 2 * LAUNCH_US * 1e-6 + 0.675 * px[l] / (GPX * 1e9)
+    for l in range(levels - 1, -1, -1):              # filtering, one launch each
+        t += LAUNCH_US * 1e-6 + 0.675 * px[l] / (GPX * 1e9)
     return t
 
 
@@ -73,7 +73,7 @@ def test_single_request_timeline():
     assert c["t_host_done"] == pytest.approx(dev + _bytes(w, h) / (D2H * 1e9), rel=1e-9)
     assert c["tick_last"] - c["tick_first"] == 2 * LEVELS - 1
     st = srv.stats()
-    assert st["ticks"] == 2 * LEVELS and st["launches"] == 3 * LEVELS and st["tick_items"] == 2 * LEVELS
+    assert st["ticks"] == 2 * LEVELS and st["launches"] == 2 * LEVELS and st["tick_items"] == 2 * LEVELS
     assert st["completed"] == 1 and st["arena_used"] == 0 and st["active"] == 0
 
 
@@ -171,7 +171,7 @@ def test_stages_per_tick_whole_cascade():
     srv.submit_request(_req(500, 400, tag=0))
     (c,) = _run(srv)
     assert c["status"] == M.MDN_OK and c["tick_first"] == c["tick_last"]
-    assert srv.stats()["launches"] == 3 * LEVELS
+    assert srv.stats()["launches"] == 2 * LEVELS
 
 
 def test_injected_launch_failure_only_fails_that_request():
