@@ -138,3 +138,30 @@ def test_server_mixes_column_walk_and_tiled_banks():
     for i, (o, w) in enumerate(zip(outs, want)):
         assert np.array_equal(o.numpy(), w), f"request {i} {SIZES[i]} bank {which[i]} differs in the mix"
     srv.close()
+
+
+def test_server_mixes_luma_and_colour_selector_banks():
+    """A luma-selector bank (its selection pass a launch of its own at the level's filtering stage)
+    served beside colour-selector banks (their selection pass in the pyramid step's launch): every
+    request equals the plain per-image denoiser bit for bit, alone and in the mix."""
+    import torch
+    import paper_1802_06130_amd as M
+    colour = _banks(M, torch)[:2]
+    luma = gpu_bank(trained_bank_multiscale(levels=3, selector="luma"), 3, coeff_dtype=torch.float16)
+    banks = colour + [luma]
+    zs = _inputs(torch, np.float16)
+    which = [(i * 2) % 3 for i in range(len(zs))]
+    want = _plain(M, banks, zs, which, M.F16)
+    srv = M.Server(banks, storage=M.F16, max_slots=4, stages_per_tick=2, hbm_budget=1 << 30)
+    alone = _alone(M, srv, zs, which)
+    for i, (a, w) in enumerate(zip(alone, want)):
+        assert np.array_equal(a, w), f"request {i} {SIZES[i]} bank {which[i]} alone differs"
+    outs = [z.new_empty(z.shape).pin_memory() for z in zs]
+    for o in outs:
+        o.fill_(-7.0)
+    reqs = [M.Server.request(z, b, o) for z, b, o in zip(zs, which, outs)]
+    done = srv.replay(reqs, synth.poisson_arrivals(5000.0, len(zs), 5400))
+    assert all(c["status"] == M.MDN_OK for c in done), done
+    for i, (o, w) in enumerate(zip(outs, want)):
+        assert np.array_equal(o.numpy(), w), f"request {i} {SIZES[i]} bank {which[i]} differs in the mix"
+    srv.close()
