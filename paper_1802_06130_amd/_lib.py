@@ -565,7 +565,9 @@ class Plan:
 
     def kernel_times(self, ins, outs=None, reps: int = 3, banks=None):
         """Mean device microseconds per launch of the batch's kernels: a list over levels of
-        (pyramid, selection, filtering), from HIP events on the plan's stream (synchronises)."""
+        (pyramid, selection, filtering), from HIP events on the plan's stream (synchronises). Where a
+        level's selection runs in its pyramid step's launch, that launch is the pyramid entry and
+        the selection entry is 0."""
         outs = outs if outs is not None else [_torch().empty_like(t) for t in ins]
         n, a, b, k = self._descs(ins, outs, banks)
         us = (ct.c_float * (3 * self.levels))()
